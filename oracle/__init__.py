@@ -24,6 +24,7 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 CHANNEL, PLATE = 0, 1
 BB_FIXED, BB_SLIP, HRFD = 0, 1, 2
 REICHARDT, SA_LAW = 0, 1
+BGK, CM = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -42,7 +43,7 @@ class Params(ctypes.Structure):
         ("q", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("nz", ctypes.c_int32), ("flow", ctypes.c_int32), ("scheme", ctypes.c_int32),
         ("law", ctypes.c_int32), ("sa_on", ctypes.c_int32), ("plate_start", ctypes.c_int32),
-        ("pad0", ctypes.c_int32),
+        ("collision", ctypes.c_int32),
         ("nu", ctypes.c_double), ("rho0", ctypes.c_double), ("force", ctypes.c_double * 3),
         ("u_inlet", ctypes.c_double), ("wall_u_bottom", ctypes.c_double * 3),
         ("wall_u_top", ctypes.c_double * 3), ("nut_init_ratio", ctypes.c_double),
@@ -56,11 +57,12 @@ class Params(ctypes.Structure):
 def params(q=9, nx=4, ny=64, nz=1, flow=CHANNEL, scheme=BB_SLIP, law=REICHARDT, sa_on=1,
            plate_start=0, nu=1e-3, rho0=1.0, force=(0.0, 0.0, 0.0), u_inlet=0.0,
            wall_u_bottom=(0.0, 0.0, 0.0), wall_u_top=(0.0, 0.0, 0.0), nut_init_ratio=3.0,
-           kappa=0.41, B=5.2, beta=0.28) -> Params:
+           kappa=0.41, B=5.2, beta=0.28, collision=BGK) -> Params:
     """Parameters with the SA constants listed after eq. 14."""
     p = Params()
     p.q, p.nx, p.ny, p.nz = q, nx, ny, nz
     p.flow, p.scheme, p.law, p.sa_on, p.plate_start = flow, scheme, law, sa_on, plate_start
+    p.collision = collision
     p.nu, p.rho0, p.u_inlet = nu, rho0, u_inlet
     p.force[:] = list(force)
     p.wall_u_bottom[:] = list(wall_u_bottom)
@@ -96,6 +98,7 @@ def lib():
         L.orc_lattice.argtypes = [ctypes.c_int, vp, vp, vp]
         L.orc_feq.argtypes = [ctypes.c_int, ctypes.c_double, vp, vp]
         L.orc_collide.argtypes = [ctypes.c_int, vp, ctypes.c_double, vp, vp, vp, vp]
+        L.orc_collide_cm.argtypes = [ctypes.c_int, vp, ctypes.c_double, vp, vp, vp, vp]
         for name in ("orc_uplus", "orc_duplus"):
             getattr(L, name).restype = ctypes.c_double
             getattr(L, name).argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -152,6 +155,17 @@ def collide(q: int, f, tau: float, force=(0.0, 0.0, 0.0)):
     rho = np.zeros(1)
     u = np.zeros(3)
     lib().orc_collide(q, _ptr(f), tau, _ptr(F), _ptr(out), _ptr(rho), _ptr(u))
+    return out, float(rho[0]), u
+
+
+def collide_cm(q: int, f, tau: float, force=(0.0, 0.0, 0.0)):
+    f = _f64(f)
+    F = np.zeros(3)
+    F[: len(force)] = force
+    out = np.zeros(q)
+    rho = np.zeros(1)
+    u = np.zeros(3)
+    lib().orc_collide_cm(q, _ptr(f), tau, _ptr(F), _ptr(out), _ptr(rho), _ptr(u))
     return out, float(rho[0]), u
 
 

@@ -113,6 +113,116 @@ void orc_collide(int q, const double *f, double tau, const double *force, double
         for (int a = 0; a < 3; ++a) u_out[a] = u[a];
 }
 
+/* Central-moment collision, eq. 7 (Sec. 2.1): k = T f with
+ * T_ji = prod_a (c_ia - u_a)^{p_ja}; k* = (I - Lambda) k + Lambda k_eq +
+ * (I - Lambda/2) R; f* = T^{-1} k*.  Lambda relaxes the deviatoric second-order
+ * central moments with omega and every other moment with 1 (for D2Q9 this is
+ * Lambda = diag[1,1,1,1,omega,omega,1,1,1] in the basis of eq. 7; D3Q19 uses the
+ * same rule on its 19 central moments).  k_eq are the central moments of the
+ * Maxwellian (fourth-order Hermite equilibrium): rho, 0, rho cs2 delta, 0,
+ * rho cs2^2; R are those of the forcing term: F in first order, cs2 F_b for
+ * the moment (2 e_a + e_b), zero otherwise.  f* is found by Gaussian
+ * elimination, T being u-dependent. */
+static const int CM_B9[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {2, 0, 0}, {0, 2, 0},
+                                {1, 1, 0}, {2, 1, 0}, {1, 2, 0}, {2, 2, 0}};
+static const int CM_B19[19][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0}, {0, 2, 0}, {0, 0, 2},
+                                  {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {2, 1, 0}, {2, 0, 1}, {1, 2, 0}, {0, 2, 1},
+                                  {1, 0, 2}, {0, 1, 2}, {2, 2, 0}, {2, 0, 2}, {0, 2, 2}};
+
+static double ipow(double b, int e)
+{
+    double r = 1.0;
+    for (int k = 0; k < e; ++k) r *= b;
+    return r;
+}
+
+/* solves A x = b in place (n <= 19), partial pivoting; returns 0 on success */
+static int gauss_solve(int n, double A[19][19], double *b)
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (A[piv][c] == 0.0) return -1;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) {
+                double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t;
+            }
+            double t = b[c]; b[c] = b[piv]; b[piv] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double m = A[r][c] / A[c][c];
+            if (m == 0.0) continue;
+            for (int k = c; k < n; ++k) A[r][k] -= m * A[c][k];
+            b[r] -= m * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int k = r + 1; k < n; ++k) s -= A[r][k] * b[k];
+        b[r] = s / A[r][r];
+    }
+    return 0;
+}
+
+void orc_collide_cm(int q, const double *f, double tau, const double *force, double *fpost,
+                    double *rho_out, double *u_out)
+{
+    int c[19 * 3], opp[19];
+    double w[19];
+    orc_lattice(q, c, w, opp);
+    const int D = q == 9 ? 2 : 3;
+    const int(*P)[3] = q == 9 ? CM_B9 : CM_B19;
+    double rho = 0.0, m[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < q; ++i) {
+        rho += f[i];
+        for (int a = 0; a < 3; ++a) m[a] += f[i] * c[3 * i + a];
+    }
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = (m[a] + 0.5 * force[a]) / rho;
+    double T[19][19], k[19], ks[19];
+    for (int j = 0; j < q; ++j) {
+        k[j] = 0.0;
+        for (int i = 0; i < q; ++i) {
+            T[j][i] = 1.0;
+            for (int a = 0; a < 3; ++a) T[j][i] *= ipow(c[3 * i + a] - u[a], P[j][a]);
+            k[j] += T[j][i] * f[i];
+        }
+    }
+    double omega = 1.0 / tau;
+    double tr = 0.0; /* trace of the second-order central moments */
+    for (int j = 0; j < q; ++j)
+        if (P[j][0] + P[j][1] + P[j][2] == 2)
+            for (int a = 0; a < D; ++a)
+                if (P[j][a] == 2) tr += k[j];
+    for (int j = 0; j < q; ++j) {
+        int ord = P[j][0] + P[j][1] + P[j][2];
+        if (ord == 0) {
+            ks[j] = rho;
+        } else if (ord == 1) {
+            int a = P[j][0] ? 0 : (P[j][1] ? 1 : 2);
+            ks[j] = 0.5 * force[a]; /* (1 - 1) k + 1 * 0 + (1 - 1/2) F_a */
+        } else if (ord == 2) {
+            int diag = P[j][0] == 2 || P[j][1] == 2 || P[j][2] == 2;
+            if (diag)
+                ks[j] = rho * CS2 + (1.0 - omega) * (k[j] - tr / D);
+            else
+                ks[j] = (1.0 - omega) * k[j];
+        } else if (ord == 3) {
+            /* moment (2 e_a + e_b): forcing central moment cs2 F_b, relaxed with 1 */
+            int b = P[j][0] == 1 ? 0 : (P[j][1] == 1 ? 1 : 2);
+            ks[j] = 0.5 * CS2 * force[b];
+        } else {
+            ks[j] = rho * CS2 * CS2;
+        }
+    }
+    for (int j = 0; j < q; ++j) fpost[j] = ks[j];
+    gauss_solve(q, T, fpost);
+    if (rho_out) *rho_out = rho;
+    if (u_out)
+        for (int a = 0; a < 3; ++a) u_out[a] = u[a];
+}
+
 /* ---------------------------------------------------------------------- */
 /* Wall laws.                                                              */
 /* ---------------------------------------------------------------------- */
@@ -622,7 +732,10 @@ static void collide_and_sa(orc *o)
                 /* nu_eff = nu + nu_t from the current nu_tilde (Sec. 2.1, after eq. 9) */
                 double nut = p->sa_on ? orc_nut(p, o->nt[cell]) : 0.0;
                 double tau = 0.5 + (p->nu + nut) / CS2;
-                orc_collide(Q, f, tau, p->force, fp, &rho, u);
+                if (p->collision == ORC_CM)
+                    orc_collide_cm(Q, f, tau, p->force, fp, &rho, u);
+                else
+                    orc_collide(Q, f, tau, p->force, fp, &rho, u);
                 for (int i = 0; i < Q; ++i) o->fpost[i * N + cell] = fp[i];
                 for (int a = 0; a < 3; ++a) o->u_cur[3 * cell + a] = u[a];
                 o->rho[cell] = rho;

@@ -30,6 +30,10 @@ extern "C" {
 #define ORC_BB_SLIP 1  /* slip-velocity bounce-back (eq. 31 with eq. 35) */
 #define ORC_HRFD 2     /* hybrid regularized reconstruction (eq. 19, 23, 26-28) */
 
+/* collision operators */
+#define ORC_BGK 0 /* BGK with Guo forcing */
+#define ORC_CM 1  /* central-moment operator of eq. 7 */
+
 /* wall laws */
 #define ORC_REICHARDT 0 /* Reichardt's law, log-law intercept B */
 #define ORC_SA_LAW 1    /* SA-consistent analytic law, eq. 15-16 */
@@ -42,7 +46,7 @@ typedef struct orc_params {
     int32_t law;         /* ORC_REICHARDT / ORC_SA_LAW */
     int32_t sa_on;       /* 1: couple Spalart-Allmaras; 0: laminar, nu_t = 0 */
     int32_t plate_start; /* first wall cell of the plate (ORC_PLATE) */
-    int32_t pad0;
+    int32_t collision;   /* ORC_BGK / ORC_CM */
     double nu;           /* molecular kinematic viscosity, lattice units */
     double rho0;         /* reference density */
     double force[3];     /* body force density F */
@@ -78,6 +82,8 @@ int orc_lattice(int q, int *c /* q*3 */, double *w /* q */, int *opp /* q */);
 void orc_feq(int q, double rho, const double *u, double *feq);
 void orc_collide(int q, const double *f, double tau, const double *force,
                  double *fpost, double *rho_out, double *u_out);
+void orc_collide_cm(int q, const double *f, double tau, const double *force,
+                    double *fpost, double *rho_out, double *u_out);
 double orc_uplus(int law, double yp, double kappa, double B);
 double orc_duplus(int law, double yp, double kappa, double B);
 double orc_solve_utau(int law, double ut, double y, double nu, double kappa, double B);

@@ -511,3 +511,105 @@ def test_plate_runs_and_stays_finite(scheme):
     assert np.all(np.isfinite(u))
     assert u[0, 0, 0, 40] < 0.97 * U
     assert np.all(o.wall()["utau"] > 0)
+
+
+# ------------------------------------------------------------ CM collision ---
+def _basis(q):
+    D = _dims(q)
+    import itertools
+    out = []
+    for e in itertools.product(range(3), repeat=D):
+        out.append(tuple(e) + (0,) * (3 - D))
+    return out
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_cm_conserves_mass_and_adds_force(q):
+    rng = np.random.default_rng(7)
+    c, w, _ = O.lattice(q)
+    D = _dims(q)
+    cc = c[:, :D].astype(float)
+    for tau in (0.5 + 1e-4, 0.8, 1.7):
+        u = 0.05 * rng.standard_normal(3)
+        u[D:] = 0
+        f = O.feq(q, 1.01, u) * (1 + 0.03 * rng.standard_normal(q))
+        F = 1e-3 * rng.standard_normal(3)
+        F[D:] = 0
+        fp, rho, um = O.collide_cm(q, f, tau, F)
+        assert abs(fp.sum() - f.sum()) < 1e-15
+        assert np.abs(fp @ cc - (f @ cc + F[:D])).max() < 1e-16
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_cm_unit_relaxation_gives_maxwellian_moments(q):
+    """With omega = 1 and no force, eq. 7 sends every central moment to its
+    equilibrium, so each supported raw moment of f* equals that of a
+    Maxwellian, rho prod_a M_pa(u_a) with M_0 = 1, M_1 = u, M_2 = cs2 + u^2."""
+    rng = np.random.default_rng(8)
+    c, w, _ = O.lattice(q)
+    D = _dims(q)
+    for _ in range(4):
+        u = 0.08 * rng.standard_normal(3)
+        u[D:] = 0
+        f = O.feq(q, 0.98, u) * (1 + 0.05 * rng.standard_normal(q))
+        fp, rho, um = O.collide_cm(q, f, 1.0)
+        M = lambda p, ua: (1.0, ua, 1 / 3 + ua * ua)[p]
+        for e in _basis(q):
+            mono = np.prod([c[:, a].astype(float) ** e[a] for a in range(3)], axis=0)
+            # monomials that vanish identically on the lattice are not moments of it
+            if not np.any(mono) or (q == 19 and sum(x > 0 for x in e) == 3):
+                continue
+            ex = rho * np.prod([M(e[a], um[a]) for a in range(3)])
+            assert abs(fp @ mono - ex) < 1e-15, e
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_cm_relaxes_deviatoric_stress_only(q):
+    """Shear (off-diagonal) and deviatoric normal central moments relax with
+    omega; their trace is reset to D rho cs2 (relaxation rate 1)."""
+    rng = np.random.default_rng(9)
+    c, w, _ = O.lattice(q)
+    D = _dims(q)
+    cc = c[:, :D].astype(float)
+    tau = 0.74
+    om = 1 / tau
+    u = 0.05 * rng.standard_normal(3)
+    u[D:] = 0
+    f = O.feq(q, 1.0, u) * (1 + 0.05 * rng.standard_normal(q))
+    fp, rho, um = O.collide_cm(q, f, tau)
+    ud = um[:D]
+
+    def central2(g):
+        cb = cc - ud
+        return np.einsum("i,ia,ib->ab", g, cb, cb)
+
+    k, ks = central2(f), central2(fp)
+    dev = lambda m: m - np.eye(D) * np.trace(m) / D
+    assert np.abs(dev(ks) - (1 - om) * dev(k)).max() < 1e-15
+    assert abs(np.trace(ks) - D * rho / 3) < 1e-15
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_cm_forcing_gives_shifted_maxwellian(q):
+    """With omega = 1 and a body force, eq. 7 returns the Maxwellian moments at
+    the post-collision velocity v = u + F/(2 rho), up to O(F^2): the forcing
+    central moments (first order F, third order cs2 F) are that Maxwellian's
+    central moments about u to first order in F."""
+    rng = np.random.default_rng(10)
+    c, w, _ = O.lattice(q)
+    D = _dims(q)
+    M = lambda p, ua: (1.0, ua, 1 / 3 + ua * ua)[p]
+    for _ in range(3):
+        u = 0.06 * rng.standard_normal(3)
+        u[D:] = 0
+        f = O.feq(q, 1.0, u) * (1 + 0.05 * rng.standard_normal(q))
+        F = 2e-3 * rng.standard_normal(3)
+        F[D:] = 0
+        fp, rho, um = O.collide_cm(q, f, 1.0, F)
+        v = um + F / (2 * rho)
+        for e in _basis(q):
+            mono = np.prod([c[:, a].astype(float) ** e[a] for a in range(3)], axis=0)
+            if not np.any(mono) or (q == 19 and sum(x > 0 for x in e) == 3):
+                continue
+            ex = rho * np.prod([M(e[a], v[a]) for a in range(3)])
+            assert abs(fp @ mono - ex) < 2e-6, (e, fp @ mono - ex)
