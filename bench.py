@@ -1,0 +1,172 @@
+"""Throughput of the fused LBM-RANS step on one MI355X.
+
+Default workload: the 3-D turbulent channel, D3Q19, 512 x 256 x 256 cells
+(streamwise x wall-normal x spanwise), FP32 storage and arithmetic, Re_tau =
+5000 with 128 cells per half channel, Ma = 0.05, BGK collision with the local
+tau from nu + nu_t (Spalart-Allmaras), slip-velocity bounce-back with
+Reichardt's law, started from Dean's bulk velocity as in the paper's channel
+runs (--amp adds a seeded random perturbation).  A step is the whole hot path:
+the fused stream-collide-SA kernel, the wall-function kernel and, every 100
+steps, the FP64 residual reduction.
+
+--calibrate-copy times a plain device-to-device copy of known size instead;
+its hardware byte counters give the scale factor for the kernel's counters.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def bytes_per_lup(q: int, precision: str) -> int:
+    """Algorithmic bytes per lattice update: every population read and written
+    once, nu_tilde read and written once, the velocity written once and read
+    once through the SA stencil."""
+    sb = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[precision]
+    tb = 8 if precision == "f64" else 4
+    D = 2 if q == 9 else 3
+    return 2 * q * sb + 2 * tb + 2 * D * tb
+
+
+def cpu_baseline(nx: int, ny: int, nz: int, lat: dict, steps: int, collision: str,
+                 amp: float) -> dict:
+    import numpy as np
+
+    import oracle as O
+    from paper_2506_03905_amd import inputs
+
+    u0 = inputs.channel_velocity(0, 3, nz, ny, nx, lat["u_bulk"], amp)
+    p = O.params(q=19, nx=nx, ny=ny, nz=nz, nu=lat["nu"], force=(lat["force"], 0, 0),
+                 scheme=O.BB_SLIP, collision={"bgk": O.BGK, "cm": O.CM}[collision])
+    o = O.Oracle(p, u0)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    del o, u0
+    _ = np
+    return {"value": nx * ny * nz * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{nx}x{ny}x{nz} slab of the same channel (same resolution, Re_tau, start), "
+                      f"{steps} steps, FP64, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f16", "bf16", "f64"])
+    ap.add_argument("--nx", type=int, default=512)
+    ap.add_argument("--ny", type=int, default=256)
+    ap.add_argument("--nz", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--collision", default="bgk", choices=["bgk", "cm"])
+    ap.add_argument("--amp", type=float, default=0.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; multi-GPU runs are not part of this build "
+              "(see DESIGN.md for how the lattice would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20)
+        a = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        a.fill_(1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        print(json.dumps({"copy_bytes": n, "ms": ms, "GBs_read_plus_write": 2 * n / ms / 1e6}))
+        return
+
+    import paper_2506_03905_amd.lbm as L
+    from paper_2506_03905_amd import inputs, units
+
+    nx, ny, nz = args.nx, args.ny, args.nz
+    lat = units.channel(5000.0, ny // 2, 0.05)
+    coll = {"bgk": L.LBM_COLL_BGK, "cm": L.LBM_COLL_CM}[args.collision]
+    p = L.lbm_params_default(precision=L.PRECISION[args.precision], scheme=L.LBM_WALL_SLIP_BB,
+                             nu=lat["nu"], force=(lat["force"], 0, 0), u_ref=lat["u_bulk"],
+                             reduce_every=100, collision=coll)
+    g = L.Lattice(L.LBM_D3Q19, nx, ny, nz, p, device="cuda:0")
+    u0 = inputs.channel_velocity(0, 3, nz, ny, nx, lat["u_bulk"], args.amp)
+    g.lbm_set_velocity(u0)
+    del u0
+    print(f"# lattice {nx}x{ny}x{nz} D3Q19 {args.precision}, nu={lat['nu']:.4e}, "
+          f"tau-1/2={3 * lat['nu']:.3e}, footprint {g.bytes / 1e9:.2f} GB", file=sys.stderr, flush=True)
+    g.lbm_step(args.warmup)
+    torch.cuda.synchronize()
+    g.lbm_set_timing(True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    t0 = time.perf_counter()
+    g.lbm_step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    tm = g.lbm_get_timing()
+    g.lbm_set_timing(False)
+    res = g.lbm_residual()
+    ncell = nx * ny * nz
+    mlups = ncell * args.steps / (ms * 1e-3) / 1e6
+    bpl = bytes_per_lup(19, args.precision)
+    k_ms = tm["step_ms"] / max(tm["step_launches"], 1)
+    achieved = bpl * ncell / (k_ms * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS (D3Q19 stream-collide + SA + slip-velocity bounce-back)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32",
+                  "f64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"3-D channel D3Q19 {nx}x{ny}x{nz}, Re_tau 5000, "
+                               f"{args.collision.upper()} + SA, slip-velocity bounce-back "
+                               f"(Reichardt), Dean start" + (f" + {args.amp:g} perturbation"
+                                                             if args.amp else ""),
+                   "cells": ncell, "collision": args.collision, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "k_step", "bytes_per_lup": bpl,
+                     "kernel_ms": round(k_ms, 4),
+                     "wall_kernel_ms": round(tm["wall_ms"] / max(tm["wall_launches"], 1), 4)},
+        "residual": {"l2_du_rel": res["l2_du_rel"], "mean_u_tau": res["mean_u_tau"],
+                     "nan_flag": res["nan_flag"]},
+        "host_wall_s": round(wall_s, 3),
+    }
+    if not args.no_cpu_baseline:
+        print("# timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(nx, ny, 4, lat, args.cpu_steps, args.collision,
+                                           args.amp)
+    _ = np
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

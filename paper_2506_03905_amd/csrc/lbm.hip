@@ -1,0 +1,1232 @@
+// lbm.hip -- gfx950 kernels and C ABI of the LBM-RANS hot path.
+//
+// One time step (Ponsin & Lozano, arXiv 2506.03905) is two launches:
+//   k_step  fused streaming (single-buffer AA pattern) + wall links
+//           (bounce-back eq. 31 with the wall velocity of eq. 35, or the
+//           regularized reconstruction eq. 19/23/26-28) + plate edges +
+//           moments (eq. 4-5) + BGK/Guo collision with tau from nu + nu_t
+//           (eq. 8, 10) + the Spalart-Allmaras update (eq. 11-14);
+//   k_wall  the per-wall-cell FP64 Newton solve for u_tau at the reference
+//           node F (Sec. 3.1, eq. 20-22), the slip velocity (eq. 35) and the
+//           SA Dirichlet value nu_tilde_B = nu kappa y_B+ (Sec. 2.2).
+// A residual reduction (mass, momentum, velocity change, mean u_tau) runs
+// every K steps in FP64 with a fixed summation order.
+//
+// AA pattern: after an even step (and after initialisation) slot A[opp(i)][x]
+// holds the post-collision f*_i(x); an odd step pulls from neighbours and
+// pushes to neighbours, leaving A[i][x + c_i] = f*_i(x).  Each slot is read and
+// written by one thread only, so one buffer suffices.  Populations that leave
+// the domain through a wall or an open boundary are parked in the cell's own
+// free slot A[opp(i)][x]; populations that cross a symmetry plane are pushed
+// to their mirrored destination.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_device.hpp"
+
+using namespace lbmd;
+
+namespace {
+
+constexpr int BLK = 256;
+constexpr int NRED = 8;        // reduction slots
+constexpr int RED_BLOCKS = 2048;
+
+// ---------------------------------------------------------------------------
+// Thread -> cell mapping.
+// Channel: flat cell index; the hardware places block b on XCD b % 8, so the
+// logical block order is remapped to give each XCD one contiguous range of
+// rows (neighbouring rows of the SA stencil then share an L2).
+// Plate: one row per group of blocks, blocks aligned to the right end of the
+// row so that columns nx-2 and nx-1 share a block (outlet exchange in LDS).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t xcd_block(uint32_t b, uint32_t nb)
+{
+    uint32_t nb8 = nb & ~7u;
+    if (b >= nb8) return b;
+    return (int64_t)(b & 7u) * (nb8 >> 3) + (b >> 3);
+}
+
+template <typename T> __device__ __forceinline__ T clamp0(T v) { return v > (T)0 ? v : (T)0; }
+
+// ---------------------------------------------------------------------------
+// k_step: one fused LBM-RANS step.
+// rd: ping-pong index of u^{n-1} / nu_tilde^n; results go to rd ^ 1.
+// ---------------------------------------------------------------------------
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC>
+__global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
+{
+    constexpr int D = Lat<Q>::D;
+    using SS = Stor<S>;
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int64_t N = P.ncell;
+    const int tid = threadIdx.x;
+
+    int x, y, z;
+    int64_t cell;
+    bool active;
+    if (!PLATE) {
+        cell = xcd_block(blockIdx.x, gridDim.x) * BLK + tid;
+        active = cell < N;
+        int64_t r = cell / nx;
+        x = (int)(cell - r * nx);
+        y = (int)(r % ny);
+        z = (int)(r / ny);
+    } else {
+        const int nseg = (nx + BLK - 1) / BLK;
+        const int row = blockIdx.x / nseg, seg = blockIdx.x - row * nseg;
+        x = nx - (nseg - seg) * BLK + tid;
+        y = row;
+        z = 0;
+        active = x >= 0;
+        cell = (int64_t)x + (int64_t)nx * y;
+    }
+
+    S *__restrict__ A = (S *)P.pops;
+    const T *__restrict__ u_rd = (const T *)P.u[rd];
+    T *__restrict__ u_wr = (T *)P.u[rd ^ 1];
+    const T *__restrict__ nt_rd = (const T *)P.nt[rd];
+    T *__restrict__ nt_wr = (T *)P.nt[rd ^ 1];
+
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int64_t oxm = (x == 0) ? (PLATE ? 0 : nx - 1) : -1;
+    const int64_t oxp = (x == nx - 1) ? (PLATE ? 0 : -(int64_t)(nx - 1)) : 1;
+    const int64_t ozm = (z == 0) ? (int64_t)(nz - 1) * sz : -sz;
+    const int64_t ozp = (z == nz - 1) ? -(int64_t)(nz - 1) * sz : sz;
+    // offset from this cell to the cell x + c (periodic wrap in x for the channel and in z)
+    auto off = [&](int ccx, int ccy, int ccz) -> int64_t {
+        return (ccx > 0 ? oxp : (ccx < 0 ? oxm : 0)) + (int64_t)ccy * sy + (ccz > 0 ? ozp : (ccz < 0 ? ozm : 0));
+    };
+
+    const bool bottom = (y == 0), top = (y == ny - 1);
+    const int64_t wi = active ? wall_index(P, x, y, z) : -1;
+    T rho_w = 0, uwv[3] = {0, 0, 0};
+    if (!HRFD && wi >= 0) {
+        rho_w = (T)P.wrho[wi];
+        uwv[0] = (T)P.uw[wi];
+        uwv[1] = (T)P.uw[P.nwall + wi];
+        uwv[2] = (T)P.uw[2 * P.nwall + wi];
+    }
+
+    // ---- gather the incoming populations (deviations f - w rho0) ----------
+    T f[Q];
+    sfor<Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int ccx = cx<Q>(i), ccy = cy<Q>(i), ccz = cz<Q>(i);
+        constexpr int io = opp<Q>(i), im = opp<Q>(mir<Q>(i));
+        const bool xopen = PLATE && ((ccx > 0 && x == 0) || (ccx < 0 && x == nx - 1));
+        const bool ycross = (ccy > 0 && bottom) || (ccy < 0 && top);
+        const bool wall = ycross && (top ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, -ccx));
+        T v = 0;
+        if (active && !xopen) {
+            if (!ODD)
+                v = SS::ld(A[i * N + cell]);
+            else if (!ycross)
+                v = SS::ld(A[io * N + cell + off(-ccx, -ccy, -ccz)]);
+            else if (wall)
+                v = SS::ld(A[i * N + cell]);
+            else
+                v = SS::ld(A[im * N + cell + off(-ccx, 0, -ccz)]);
+            // eq. 31: f_i = f*_opp(i) + 2 w_i rho_w (c_i . u_w) / cs2
+            if (!HRFD && wall && wi >= 0)
+                v += (T)(6.0 * wgt<Q>(i)) * rho_w * ((T)ccx * uwv[0] + (T)ccy * uwv[1] + (T)ccz * uwv[2]);
+        }
+        f[i] = v;
+    });
+
+    // ---- plate edges: outlet copy through LDS, Zou-He inlet ---------------
+    if (PLATE) {
+        __shared__ T xch[3][BLK];
+        if (active && x == nx - 2) {
+            xch[0][tid] = f[2];
+            xch[1][tid] = f[6];
+            xch[2][tid] = f[8];
+        }
+        __syncthreads();
+        if (active && x == nx - 1) {
+            f[2] = xch[0][tid - 1];
+            f[6] = xch[1][tid - 1];
+            f[8] = xch[2][tid - 1];
+        }
+        if (active && x == 0) {
+            // Zou-He, u = (U, 0): the known weights sum to 1 in deviation form
+            const T U = (T)P.u_inlet, r0 = (T)P.rho0;
+            T s = f[0] + f[3] + f[4] + (T)2 * (f[2] + f[6] + f[8]);
+            T rho = (r0 + s) / ((T)1 - U);
+            f[1] = f[2] + (T)(2.0 / 3.0) * rho * U;
+            f[5] = f[6] - (T)0.5 * (f[3] - f[4]) + (T)(1.0 / 6.0) * rho * U;
+            f[7] = f[8] + (T)0.5 * (f[3] - f[4]) + (T)(1.0 / 6.0) * rho * U;
+        }
+    }
+    if (!active) return;
+
+    const T nt0 = P.sa_on ? nt_rd[cell] : (T)0;
+
+    // ---- HRFD: regularized reconstruction at the wall cells (D2Q9) --------
+    if (HRFD && wi >= 0) {
+        const int side = bottom ? -1 : 1;  // outward normal n = (0, side)
+        T spar = f[0] + f[1] + f[2];
+        T sperp = side < 0 ? (f[4] + f[6] + f[7]) : (f[3] + f[5] + f[8]);
+        const T rhoB = (T)P.rho0 + spar + (T)2 * sperp;  // eq. 23 with u_B . n = 0
+        const T tx = (T)P.tdir[wi];
+        const T ubwf = (T)P.ubwf[wi];
+        const T uBx = ubwf * tx;
+        const int64_t F = cell - side * sy, FF = cell - 2 * side * sy;
+        const T uFt = u_rd[F] * tx, uFFt = u_rd[FF] * tx;  // t = (tx, 0)
+        const T gfd = ((T)-3 * ubwf + (T)4 * uFt - uFFt) * (T)0.5;            // eq. 28
+        const T G = (T)P.beta * (T)P.gan[wi] + ((T)1 - (T)P.beta) * gfd;     // eq. 27
+        // tangential derivative of the wall-function u_x along the wall
+        int64_t wl = -1, wr = -1;
+        if (P.flow == FLOW_CHANNEL) {
+            const int xl = x == 0 ? nx - 1 : x - 1, xr = x == nx - 1 ? 0 : x + 1;
+            wl = wall_index(P, xl, y, z);
+            wr = wall_index(P, xr, y, z);
+        } else {
+            wl = x - 1 >= P.plate_start ? wi - 1 : -1;
+            wr = x + 1 < nx ? wi + 1 : -1;
+        }
+        T dudx = 0;
+        if (wl >= 0 && wr >= 0)
+            dudx = ((T)(P.ubwf[wr] * P.tdir[wr]) - (T)(P.ubwf[wl] * P.tdir[wl])) * (T)0.5;
+        else if (wr >= 0)
+            dudx = (T)(P.ubwf[wr] * P.tdir[wr]) - uBx;
+        else if (wl >= 0)
+            dudx = uBx - (T)(P.ubwf[wl] * P.tdir[wl]);
+        // S_xy = G t_x n'_y / 2 with the inward normal n' = (0, -side)
+        const T Sxy = (T)0.5 * G * tx * (T)(-side);
+        const T Sxx = dudx, Syy = -dudx;
+        const T nutB = P.sa_on ? nut_of<T>(P, nt0) : (T)0;
+        const T tauB = (T)0.5 + (T)3 * ((T)P.nu + nutB);
+        const T uu = uBx * uBx;
+        sfor<Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const T ccx = (T)cx<Q>(i), ccy = (T)cy<Q>(i);
+            const T cu = ccx * uBx;
+            const T w = (T)wgt<Q>(i);
+            const T feqd = w * ((rhoB - (T)P.rho0) + rhoB * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu));
+            const T QS = (ccx * ccx - (T)(1.0 / 3.0)) * Sxx + (ccy * ccy - (T)(1.0 / 3.0)) * Syy + (T)2 * ccx * ccy * Sxy;
+            f[i] = feqd - w * rhoB * tauB * (T)3 * QS;  // eq. 26, deviation form
+        });
+    }
+
+    // ---- moments (eq. 4-5) ------------------------------------------------
+    T drho = 0, jx = 0, jy = 0, jz = 0;
+    sfor<Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        drho += f[i];
+        if constexpr (cx<Q>(i) > 0) jx += f[i];
+        if constexpr (cx<Q>(i) < 0) jx -= f[i];
+        if constexpr (cy<Q>(i) > 0) jy += f[i];
+        if constexpr (cy<Q>(i) < 0) jy -= f[i];
+        if constexpr (cz<Q>(i) > 0) jz += f[i];
+        if constexpr (cz<Q>(i) < 0) jz -= f[i];
+    });
+    const T rho = (T)P.rho0 + drho;
+    const T Fx = (T)P.fx, Fy = (T)P.fy, Fz = (T)P.fz;
+    const T inv = (T)1 / rho;
+    const T ux = (jx + (T)0.5 * Fx) * inv, uy = (jy + (T)0.5 * Fy) * inv, uz = D == 3 ? (jz + (T)0.5 * Fz) * inv : (T)0;
+
+    // ---- collision with tau_eff = 1/2 + (nu + nu_t)/cs2 -------------------------
+    const T nut = P.sa_on ? nut_of<T>(P, nt0) : (T)0;
+    const T omega = (T)1 / ((T)0.5 + (T)3 * ((T)P.nu + nut));
+    if constexpr (CMC) {
+        // central-moment operator, eq. 7
+        const T uvec[3] = {ux, uy, uz}, Fv[3] = {Fx, Fy, Fz};
+        cm_collide<Q, T>(f, drho, rho, uvec, Fv, omega);
+    } else {
+        // BGK with Guo forcing
+        const T uu = ux * ux + uy * uy + uz * uz;
+        const T fpref = (T)1 - (T)0.5 * omega;
+        const T uF = ux * Fx + uy * Fy + uz * Fz;
+        sfor<Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const T ccx = (T)cx<Q>(i), ccy = (T)cy<Q>(i), ccz = (T)cz<Q>(i);
+            const T w = (T)wgt<Q>(i);
+            const T cu = ccx * ux + ccy * uy + ccz * uz;
+            const T feqd = w * (drho + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu));
+            const T cF = ccx * Fx + ccy * Fy + ccz * Fz;
+            const T src = fpref * w * ((T)3 * (cF - uF) + (T)9 * cu * cF);
+            f[i] = f[i] - omega * (f[i] - feqd) + src;
+        });
+    }
+    // ---- store (AA pattern) ---------------------------------------------------
+    sfor<Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int ccxi = cx<Q>(i), ccyi = cy<Q>(i), cczi = cz<Q>(i);
+        constexpr int io = opp<Q>(i), im = mir<Q>(i);
+        const T fp = f[i];
+        if (!ODD) {
+            A[io * N + cell] = SS::st(fp);
+        } else {
+            const bool xopen = PLATE && ((ccxi > 0 && x == nx - 1) || (ccxi < 0 && x == 0));
+            const bool ycross = (ccyi < 0 && bottom) || (ccyi > 0 && top);
+            if (xopen) {
+                A[io * N + cell] = SS::st(fp);
+            } else if (!ycross) {
+                A[i * N + cell + off(ccxi, ccyi, cczi)] = SS::st(fp);
+            } else {
+                const bool wall = top ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, ccxi);
+                if (wall)
+                    A[io * N + cell] = SS::st(fp);
+                else
+                    A[im * N + cell + off(ccxi, 0, cczi)] = SS::st(fp);
+            }
+        }
+    });
+    u_wr[cell] = ux;
+    u_wr[N + cell] = uy;
+    if (D == 3) u_wr[2 * N + cell] = uz;
+    if (wi >= 0) P.wrho[wi] = (double)rho;
+
+    // ---- Spalart-Allmaras update from nu_tilde^n and u^{n-1} -------------------
+    if (!P.sa_on) return;
+    const bool dirichlet = (wi >= 0) || (PLATE && x == 0);
+    if (dirichlet) {
+        if (wi < 0) nt_wr[cell] = nt0;  // plate inlet keeps its value; walls: k_wall
+        return;
+    }
+    T ntm[3], ntp[3], g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    // x neighbours (plate outlet: zero-gradient copy)
+    {
+        const int64_t cm = cell + oxm, cp = cell + oxp;  // plate: oxp = 0 at the outlet
+        ntm[0] = nt_rd[cm];
+        ntp[0] = nt_rd[cp];
+        g[1][0] = (u_rd[N + cp] - u_rd[N + cm]) * (T)0.5;
+        if (D == 3) g[2][0] = (u_rd[2 * N + cp] - u_rd[2 * N + cm]) * (T)0.5;
+    }
+    // y neighbours (plate symmetry planes: mirror image, same tangential velocity)
+    {
+        const int64_t cm = (y == 0) ? cell : cell - sy, cp = (y == ny - 1) ? cell : cell + sy;
+        ntm[1] = nt_rd[cm];
+        ntp[1] = nt_rd[cp];
+        g[0][1] = (u_rd[cp] - u_rd[cm]) * (T)0.5;
+        if (D == 3) g[2][1] = (u_rd[2 * N + cp] - u_rd[2 * N + cm]) * (T)0.5;
+    }
+    if (D == 3) {
+        const int64_t cm = cell + ozm, cp = cell + ozp;
+        ntm[2] = nt_rd[cm];
+        ntp[2] = nt_rd[cp];
+        g[0][2] = (u_rd[cp] - u_rd[cm]) * (T)0.5;
+        g[1][2] = (u_rd[N + cp] - u_rd[N + cm]) * (T)0.5;
+    }
+    T u0[3] = {u_rd[cell], u_rd[N + cell], D == 3 ? u_rd[2 * N + cell] : (T)0};
+    const T d = wall_dist<T>(P, x, y);
+    const T rhs = sa_rhs<D, T>(P, nt0, ntm, ntp, u0, g, d);
+    nt_wr[cell] = clamp0(nt0 + rhs);
+}
+
+// ---------------------------------------------------------------------------
+// k_wall: wall function at every wall cell from u^n (buffer wr); writes the
+// Dirichlet nu_tilde_B into nu_tilde buffer wr.
+// ---------------------------------------------------------------------------
+template <int D, typename T> __global__ void __launch_bounds__(BLK) k_wall(KP P, int wr)
+{
+    const int64_t w = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (w >= P.nwall) return;
+    const int nx = P.nx, ny = P.ny;
+    const int64_t N = P.ncell, sy = nx;
+    int x, z, side;
+    if (P.flow == FLOW_CHANNEL) {
+        const int64_t per = (int64_t)nx * P.nz;
+        side = w < per ? -1 : 1;
+        const int64_t r = w < per ? w : w - per;
+        x = (int)(r % nx);
+        z = (int)(r / nx);
+    } else {
+        side = -1;
+        x = P.plate_start + (int)w;
+        z = 0;
+    }
+    const int yB = side < 0 ? 0 : ny - 1;
+    const int64_t B = x + (int64_t)nx * (yB + (int64_t)ny * z);
+    const int64_t F = B - side * sy;
+    const T *u = (const T *)P.u[wr];
+    const double uFx = (double)u[F], uFz = D == 3 ? (double)u[2 * N + F] : 0.0;
+    const double uBx = (double)u[B], uBz = D == 3 ? (double)u[2 * N + B] : 0.0;
+    const double ut = sqrt(uFx * uFx + uFz * uFz);
+    double tx = 1.0, tz = 0.0;
+    if (ut > 0.0) {
+        tx = uFx / ut;
+        tz = uFz / ut;
+    }
+    const double utau = solve_utau(P, ut, 1.5, P.utau[w]);
+    const double yBp = 0.5 * utau / P.nu;
+    double uw[3] = {0.0, 0.0, 0.0};
+    if (P.scheme == WALL_FIXED) {
+        const double *s = side < 0 ? P.wall_u_bottom : P.wall_u_top;
+        uw[0] = s[0];
+        uw[1] = s[1];
+        uw[2] = s[2];
+    } else if (P.scheme == WALL_SLIP) {
+        // eq. 35 with nu_t|B = nu kappa y_B+ and Delta_w = y_B = 1/2
+        const double s = utau * utau * 0.5 / (P.nu * (1.0 + P.kappa * yBp));
+        uw[0] = uBx - s * tx;
+        uw[2] = uBz - s * tz;
+    } else {
+        P.ubwf[w] = utau * uplus(P, yBp);
+        P.gan[w] = utau * utau / P.nu * duplus(P, yBp);
+    }
+    P.utau[w] = utau;
+    P.tdir[w] = tx;
+    P.tdir[P.nwall + w] = 0.0;
+    P.tdir[2 * P.nwall + w] = tz;
+    P.uw[w] = uw[0];
+    P.uw[P.nwall + w] = uw[1];
+    P.uw[2 * P.nwall + w] = uw[2];
+    if (P.sa_on) ((T *)P.nt[wr])[B] = (T)(P.nu * P.kappa * yBp);
+}
+
+// ---------------------------------------------------------------------------
+// Canonical post-collision population f*_i(x) (deviation) of the last step.
+// odd_state: the last step was odd (pushed layout).
+// ---------------------------------------------------------------------------
+template <int Q, int i, typename S, typename T>
+__device__ __forceinline__ T canon_f(const KP &P, const S *A, int x, int y, int z, int64_t cell, bool odd_state)
+{
+    using SS = Stor<S>;
+    const int64_t N = P.ncell;
+    constexpr int io = opp<Q>(i), im = mir<Q>(i);
+    if (!odd_state) return SS::ld(A[io * N + cell]);
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    constexpr int ccx = cx<Q>(i), ccy = cy<Q>(i), ccz = cz<Q>(i);
+    const bool plate = P.flow == FLOW_PLATE;
+    const bool xopen = plate && ((ccx > 0 && x == nx - 1) || (ccx < 0 && x == 0));
+    const bool ycross = (ccy < 0 && y == 0) || (ccy > 0 && y == ny - 1);
+    if (xopen) return SS::ld(A[io * N + cell]);
+    int xd = x + ccx, zd = z + ccz;
+    if (!plate) xd = (xd + nx) % nx;
+    zd = (zd + nz) % nz;
+    if (!ycross) return SS::ld(A[i * N + xd + (int64_t)nx * (y + ccy + (int64_t)ny * zd)]);
+    const bool wall = (y == ny - 1 && ccy > 0) ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, ccx);
+    if (wall) return SS::ld(A[io * N + cell]);
+    return SS::ld(A[im * N + xd + (int64_t)nx * (y + (int64_t)ny * zd)]);
+}
+
+template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) k_export_f(KP P, bool odd_state, double *out)
+{
+    const int64_t cell = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (cell >= P.ncell) return;
+    const int64_t r = cell / P.nx;
+    const int x = (int)(cell - r * P.nx), y = (int)(r % P.ny), z = (int)(r / P.ny);
+    const S *A = (const S *)P.pops;
+    sfor<Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        out[i * P.ncell + cell] = (double)canon_f<Q, i, S, T>(P, A, x, y, z, cell, odd_state) + wgt<Q>(i) * P.rho0;
+    });
+}
+
+template <int Q, typename S, typename T>
+__global__ void __launch_bounds__(BLK) k_export_moments(KP P, bool odd_state, int cur, double *rho, double *u, double *nut)
+{
+    constexpr int D = Lat<Q>::D;
+    const int64_t cell = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (cell >= P.ncell) return;
+    const int64_t N = P.ncell;
+    if (rho) {
+        const int64_t r = cell / P.nx;
+        const int x = (int)(cell - r * P.nx), y = (int)(r % P.ny), z = (int)(r / P.ny);
+        const S *A = (const S *)P.pops;
+        double s = 0.0;
+        sfor<Q>([&](auto ic) { s += (double)canon_f<Q, decltype(ic)::value, S, T>(P, A, x, y, z, cell, odd_state); });
+        rho[cell] = P.rho0 + s;
+    }
+    if (u) {
+        const T *uc = (const T *)P.u[cur];
+        for (int a = 0; a < D; ++a) u[a * N + cell] = (double)uc[a * N + cell];
+    }
+    if (nut) {
+        const T nt = ((const T *)P.nt[cur])[cell];
+        nut[cell] = P.sa_on ? (double)nut_of<T>(P, nt) : 0.0;
+    }
+}
+
+template <typename T> __global__ void __launch_bounds__(BLK) k_export_nt(KP P, int cur, double *out)
+{
+    const int64_t cell = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (cell >= P.ncell) return;
+    out[cell] = (double)((const T *)P.nt[cur])[cell];
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: f*_i = f_eq(rho0, u0) in the even layout, u^0 = u0,
+// nu_tilde = ratio * nu.  u0: device doubles (D*ncell) or NULL (uniform).
+// ---------------------------------------------------------------------------
+template <int Q, typename S, typename T>
+__global__ void __launch_bounds__(BLK) k_init(KP P, const double *u0, double ux0, double uy0, double uz0, double ntinit)
+{
+    constexpr int D = Lat<Q>::D;
+    using SS = Stor<S>;
+    const int64_t cell = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (cell >= P.ncell) return;
+    const int64_t N = P.ncell;
+    double u[3] = {ux0, uy0, D == 3 ? uz0 : 0.0};
+    if (u0)
+        for (int a = 0; a < D; ++a) u[a] = u0[a * N + cell];
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    S *A = (S *)P.pops;
+    sfor<Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const double cu = cx<Q>(i) * u[0] + cy<Q>(i) * u[1] + cz<Q>(i) * u[2];
+        const double fd = wgt<Q>(i) * P.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        A[opp<Q>(i) * N + cell] = SS::st((T)fd);
+    });
+    T *u_0 = (T *)P.u[0], *us = (T *)P.usnap;
+    for (int a = 0; a < D; ++a) {
+        u_0[a * N + cell] = (T)u[a];
+        us[a * N + cell] = (T)u[a];
+    }
+    ((T *)P.nt[0])[cell] = (T)ntinit;
+    ((T *)P.nt[1])[cell] = (T)ntinit;
+}
+
+__global__ void k_init_wall(KP P)
+{
+    const int64_t w = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (w >= P.nwall) return;
+    P.utau[w] = 0.0;
+    P.wrho[w] = P.rho0;
+    P.ubwf[w] = 0.0;
+    P.gan[w] = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        P.tdir[a * P.nwall + w] = a == 0 ? 1.0 : 0.0;
+        P.uw[a * P.nwall + w] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reduction: per-block FP64 partials in a fixed tree order, then one block.
+// slots: 0 sum(rho - rho0), 1-3 sum(rho u), 4 sum |u - usnap|^2, 5 sum |u|^2,
+// 6 bad-value count.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_sum(double (*sh)[BLK], double *v, int nv)
+{
+    const int t = threadIdx.x;
+    for (int k = 0; k < nv; ++k) sh[k][t] = v[k];
+    __syncthreads();
+    for (int s = BLK / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (int k = 0; k < nv; ++k) sh[k][t] += sh[k][t + s];
+        __syncthreads();
+    }
+}
+
+template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) k_reduce(KP P, bool odd_state, int cur)
+{
+    constexpr int D = Lat<Q>::D;
+    __shared__ double sh[7][BLK];
+    const int64_t N = P.ncell;
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    const S *A = (const S *)P.pops;
+    const T *uc = (const T *)P.u[cur];
+    T *us = (T *)P.usnap;
+    for (int64_t cell = (int64_t)blockIdx.x * BLK + threadIdx.x; cell < N; cell += (int64_t)gridDim.x * BLK) {
+        const int64_t r = cell / P.nx;
+        const int x = (int)(cell - r * P.nx), y = (int)(r % P.ny), z = (int)(r / P.ny);
+        double drho = 0.0;
+        sfor<Q>([&](auto ic) { drho += (double)canon_f<Q, decltype(ic)::value, S, T>(P, A, x, y, z, cell, odd_state); });
+        const double rho = P.rho0 + drho;
+        double uu = 0.0, du = 0.0;
+        bool bad = !(rho > 0.0) || !isfinite(rho);
+        for (int a = 0; a < D; ++a) {
+            const double ua = (double)uc[a * N + cell];
+            const double d = ua - (double)us[a * N + cell];
+            us[a * N + cell] = uc[a * N + cell];
+            acc[1 + a] += rho * ua;
+            uu += ua * ua;
+            du += d * d;
+            bad = bad || !isfinite(ua);
+        }
+        acc[0] += drho;
+        acc[4] += du;
+        acc[5] += uu;
+        acc[6] += bad ? 1.0 : 0.0;
+    }
+    block_sum(sh, acc, 7);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 7; ++k) P.partials[blockIdx.x * NRED + k] = sh[k][0];
+}
+
+__global__ void __launch_bounds__(BLK) k_reduce_final(KP P, int nblocks, int slot)
+{
+    __shared__ double sh[8][BLK];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += BLK)
+        for (int k = 0; k < 7; ++k) acc[k] += P.partials[b * NRED + k];
+    for (int64_t w = threadIdx.x; w < P.nwall; w += BLK) acc[7] += P.utau[w];
+    block_sum(sh, acc, 8);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 8; ++k) P.result[slot * NRED + k] = sh[k][0];
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIPCHK(expr)                                                                                     \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return fail(LBM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+int storage_bytes(int precision)
+{
+    switch (precision) {
+    case LBM_F64: return 8;
+    case LBM_F32: return 4;
+    case LBM_F16: return 2;
+    case LBM_BF16: return 2;
+    default: return -1;
+    }
+}
+
+struct Layout {
+    int64_t pops, u0, u1, nt0, nt1, usnap, utau, tdir, uw, wrho, ubwf, gan, partials, result, total;
+};
+
+int64_t nwall_of(int flow, int nx, int nz, int plate_start)
+{
+    if (flow == LBM_FLOW_CHANNEL) return 2LL * nx * nz;
+    int x0 = plate_start < 0 ? 0 : plate_start;
+    return nx > x0 ? (int64_t)(nx - x0) : 0;
+}
+
+bool make_layout(int Q, int nx, int ny, int nz, const lbm_params_t *p, Layout *L)
+{
+    const int sb = storage_bytes(p->precision);
+    if (sb < 0) return false;
+    const int tb = p->precision == LBM_F64 ? 8 : 4;
+    const int D = Q == 9 ? 2 : 3;
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t nw = nwall_of(p->flow, nx, nz, p->plate_start);
+    int64_t o = 0;
+    L->pops = o; o = align256(o + (int64_t)Q * N * sb);
+    L->u0 = o; o = align256(o + (int64_t)D * N * tb);
+    L->u1 = o; o = align256(o + (int64_t)D * N * tb);
+    L->nt0 = o; o = align256(o + N * tb);
+    L->nt1 = o; o = align256(o + N * tb);
+    L->usnap = o; o = align256(o + (int64_t)D * N * tb);
+    L->utau = o; o = align256(o + (nw + 1) * 8);
+    L->tdir = o; o = align256(o + 3 * (nw + 1) * 8);
+    L->uw = o; o = align256(o + 3 * (nw + 1) * 8);
+    L->wrho = o; o = align256(o + (nw + 1) * 8);
+    L->ubwf = o; o = align256(o + (nw + 1) * 8);
+    L->gan = o; o = align256(o + (nw + 1) * 8);
+    L->partials = o; o = align256(o + (int64_t)RED_BLOCKS * NRED * 8);
+    L->result = o; o = align256(o + 32 * 8);
+    L->total = o;
+    return true;
+}
+
+}  // namespace
+
+struct lbm {
+    int Q, D, nx, ny, nz;
+    lbm_params_t p;
+    KP kp;
+    Layout L;
+    char *base;
+    int64_t bytes;
+    hipStream_t stream;
+    int64_t step;
+    int64_t last_reduce_step;   // step of the last reduction (-1: none)
+    int64_t prev_reduce_step;
+    int reduce_count;
+    bool diverged;
+    bool timing;
+    std::vector<hipEvent_t> ev_step, ev_wall;  // pairs
+    size_t n_step_ev, n_wall_ev;
+    double acc_step_ms, acc_wall_ms;
+    int64_t acc_step_n, acc_wall_n;
+};
+
+namespace {
+
+template <int Q, typename S, typename T> struct Impl {
+    static constexpr int D = Lat<Q>::D;
+    template <bool PLATE, bool HRFD> static void (*pick(bool odd, bool cm))(KP, int)
+    {
+        if (cm) return odd ? k_step<Q, S, T, true, PLATE, HRFD, true> : k_step<Q, S, T, false, PLATE, HRFD, true>;
+        return odd ? k_step<Q, S, T, true, PLATE, HRFD, false> : k_step<Q, S, T, false, PLATE, HRFD, false>;
+    }
+    static int step(lbm *h, bool odd, int rd)
+    {
+        const KP &P = h->kp;
+        const bool plate = h->p.flow == LBM_FLOW_PLATE;
+        const bool hrfd = h->p.scheme == LBM_WALL_HRFD;
+        dim3 grid;
+        if (plate)
+            grid = dim3((unsigned)(h->ny * ((h->nx + BLK - 1) / BLK)));
+        else
+            grid = dim3((unsigned)((P.ncell + BLK - 1) / BLK));
+        const bool cm = h->p.collision == LBM_COLL_CM;
+        void (*kern)(KP, int) = nullptr;
+        if constexpr (Q == 9) {
+            if (plate) {
+                if (hrfd) kern = pick<true, true>(odd, cm);
+                else kern = pick<true, false>(odd, cm);
+            } else {
+                if (hrfd) kern = pick<false, true>(odd, cm);
+                else kern = pick<false, false>(odd, cm);
+            }
+        } else {
+            kern = pick<false, false>(odd, cm);
+        }
+        hipLaunchKernelGGL(kern, grid, dim3(BLK), 0, h->stream, P, rd);
+        HIPCHK(hipGetLastError());
+        return LBM_OK;
+    }
+    static int wall(lbm *h, int wr)
+    {
+        if (h->kp.nwall == 0) return LBM_OK;
+        dim3 grid((unsigned)((h->kp.nwall + BLK - 1) / BLK));
+        hipLaunchKernelGGL((k_wall<D, T>), grid, dim3(BLK), 0, h->stream, h->kp, wr);
+        HIPCHK(hipGetLastError());
+        return LBM_OK;
+    }
+    static int init(lbm *h, const double *u0dev)
+    {
+        dim3 grid((unsigned)((h->kp.ncell + BLK - 1) / BLK));
+        const double ntinit = h->p.sa_on ? h->p.nut_init_ratio * h->p.nu : 0.0;
+        const double *ui = h->p.u_init;
+        hipLaunchKernelGGL((k_init<Q, S, T>), grid, dim3(BLK), 0, h->stream, h->kp, u0dev, ui[0], ui[1], ui[2], ntinit);
+        HIPCHK(hipGetLastError());
+        if (h->kp.nwall > 0) {
+            dim3 gw((unsigned)((h->kp.nwall + BLK - 1) / BLK));
+            hipLaunchKernelGGL(k_init_wall, gw, dim3(BLK), 0, h->stream, h->kp);
+            HIPCHK(hipGetLastError());
+        }
+        return wall(h, 0);
+    }
+    static int reduce(lbm *h, bool odd_state, int cur, int slot)
+    {
+        int nb = (int)((h->kp.ncell + BLK - 1) / BLK);
+        if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+        hipLaunchKernelGGL((k_reduce<Q, S, T>), dim3(nb), dim3(BLK), 0, h->stream, h->kp, odd_state, cur);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLK), 0, h->stream, h->kp, nb, slot);
+        HIPCHK(hipGetLastError());
+        return LBM_OK;
+    }
+    static int moments(lbm *h, bool odd_state, int cur, double *rho, double *u, double *nut)
+    {
+        dim3 grid((unsigned)((h->kp.ncell + BLK - 1) / BLK));
+        hipLaunchKernelGGL((k_export_moments<Q, S, T>), grid, dim3(BLK), 0, h->stream, h->kp, odd_state, cur, rho, u, nut);
+        HIPCHK(hipGetLastError());
+        return LBM_OK;
+    }
+    static int nt(lbm *h, int cur, double *out)
+    {
+        dim3 grid((unsigned)((h->kp.ncell + BLK - 1) / BLK));
+        hipLaunchKernelGGL((k_export_nt<T>), grid, dim3(BLK), 0, h->stream, h->kp, cur, out);
+        HIPCHK(hipGetLastError());
+        return LBM_OK;
+    }
+    static int pops(lbm *h, bool odd_state, double *out)
+    {
+        dim3 grid((unsigned)((h->kp.ncell + BLK - 1) / BLK));
+        hipLaunchKernelGGL((k_export_f<Q, S, T>), grid, dim3(BLK), 0, h->stream, h->kp, odd_state, out);
+        HIPCHK(hipGetLastError());
+        return LBM_OK;
+    }
+};
+
+#define LBM_DISPATCH(h, fn, ...)                                                                 \
+    ((h)->Q == 9 ? ((h)->p.precision == LBM_F64   ? Impl<9, double, double>::fn(__VA_ARGS__)    \
+                    : (h)->p.precision == LBM_F32 ? Impl<9, float, float>::fn(__VA_ARGS__)      \
+                    : (h)->p.precision == LBM_F16 ? Impl<9, _Float16, float>::fn(__VA_ARGS__)   \
+                                                  : Impl<9, bf16s, float>::fn(__VA_ARGS__))     \
+                 : ((h)->p.precision == LBM_F64   ? Impl<19, double, double>::fn(__VA_ARGS__)   \
+                    : (h)->p.precision == LBM_F32 ? Impl<19, float, float>::fn(__VA_ARGS__)     \
+                    : (h)->p.precision == LBM_F16 ? Impl<19, _Float16, float>::fn(__VA_ARGS__)  \
+                                                  : Impl<19, bf16s, float>::fn(__VA_ARGS__)))
+
+int check_params(int lattice, int nx, int ny, int nz, const lbm_params_t *p)
+{
+    if (!p) return fail(LBM_EINVAL, "params is NULL");
+    if (p->size != (int32_t)sizeof(lbm_params_t) || p->version != LBM_PARAMS_VERSION)
+        return fail(LBM_EINVAL, "params size/version mismatch (use lbm_params_default)");
+    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return fail(LBM_EINVAL, "unknown lattice %d", lattice);
+    if (nx < 1 || ny < 4 || nz < 1) return fail(LBM_EINVAL, "bad dimensions %d x %d x %d", nx, ny, nz);
+    if (lattice == LBM_D2Q9 && nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
+    if (storage_bytes(p->precision) < 0) return fail(LBM_EINVAL, "unknown precision %d", p->precision);
+    if (p->flow != LBM_FLOW_CHANNEL && p->flow != LBM_FLOW_PLATE) return fail(LBM_EINVAL, "unknown flow %d", p->flow);
+    if (p->flow == LBM_FLOW_PLATE && (lattice != LBM_D2Q9 || nx < 4))
+        return fail(LBM_EINVAL, "the plate needs D2Q9 and nx >= 4");
+    if (p->scheme < LBM_WALL_FIXED_BB || p->scheme > LBM_WALL_HRFD) return fail(LBM_EINVAL, "unknown wall scheme");
+    if (p->scheme == LBM_WALL_HRFD && lattice != LBM_D2Q9) return fail(LBM_EINVAL, "HRFD is D2Q9 only");
+    if (p->law != LBM_LAW_REICHARDT && p->law != LBM_LAW_SA) return fail(LBM_EINVAL, "unknown wall law");
+    if (!(p->nu > 0.0)) return fail(LBM_EINVAL, "nu must be > 0 (tau_eff > 1/2)");
+    if (!(p->rho0 > 0.0)) return fail(LBM_EINVAL, "rho0 must be > 0");
+    if (p->reduce_every < 0) return fail(LBM_EINVAL, "reduce_every must be >= 0");
+    if (p->collision != LBM_COLL_BGK && p->collision != LBM_COLL_CM) return fail(LBM_EINVAL, "unknown collision %d", p->collision);
+    if ((int64_t)nx * ny * nz > (int64_t)1 << 40) return fail(LBM_EINVAL, "lattice too large");
+    return LBM_OK;
+}
+
+void fill_kp(lbm *h)
+{
+    KP &k = h->kp;
+    const lbm_params_t &p = h->p;
+    memset(&k, 0, sizeof k);
+    k.nx = h->nx;
+    k.ny = h->ny;
+    k.nz = h->nz;
+    k.flow = p.flow;
+    k.ncell = (int64_t)h->nx * h->ny * h->nz;
+    k.scheme = p.scheme;
+    k.law = p.law;
+    k.sa_on = p.sa_on;
+    k.plate_start = p.plate_start < 0 ? 0 : p.plate_start;
+    k.nwall = nwall_of(p.flow, h->nx, h->nz, p.plate_start);
+    k.nu = p.nu;
+    k.rho0 = p.rho0;
+    k.fx = p.force[0];
+    k.fy = p.force[1];
+    k.fz = h->D == 3 ? p.force[2] : 0.0;
+    k.u_inlet = p.u_inlet;
+    k.kappa = p.kappa;
+    k.B = p.B;
+    k.beta = p.beta;
+    k.reC = p.B - log(p.kappa) / p.kappa;
+    k.cb1 = p.cb1;
+    k.cb2 = p.cb2;
+    k.sigma = p.sigma;
+    k.cw1 = p.cb1 / (p.kappa * p.kappa) + (1.0 + p.cb2) / p.sigma;  // definition after eq. 14
+    k.cw2 = p.cw2;
+    k.cw3 = p.cw3;
+    k.cv1 = p.cv1;
+    k.rlim = p.rlim;
+    for (int a = 0; a < 3; ++a) {
+        k.wall_u_bottom[a] = p.wall_u_bottom[a];
+        k.wall_u_top[a] = p.wall_u_top[a];
+    }
+    const Layout &L = h->L;
+    char *b = h->base;
+    k.pops = b + L.pops;
+    k.u[0] = b + L.u0;
+    k.u[1] = b + L.u1;
+    k.nt[0] = b + L.nt0;
+    k.nt[1] = b + L.nt1;
+    k.usnap = b + L.usnap;
+    k.utau = (double *)(b + L.utau);
+    k.tdir = (double *)(b + L.tdir);
+    k.uw = (double *)(b + L.uw);
+    k.wrho = (double *)(b + L.wrho);
+    k.ubwf = (double *)(b + L.ubwf);
+    k.gan = (double *)(b + L.gan);
+    k.partials = (double *)(b + L.partials);
+    k.result = (double *)(b + L.result);
+}
+
+int run_init(lbm *h, const double *u0dev)
+{
+    h->step = 0;
+    h->last_reduce_step = -1;
+    h->prev_reduce_step = 0;
+    h->reduce_count = 0;
+    h->diverged = false;
+    return LBM_DISPATCH(h, init, h, u0dev);
+}
+
+int record(lbm *h, std::vector<hipEvent_t> &v, size_t &n)
+{
+    if (n >= v.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        v.push_back(e);
+    }
+    HIPCHK(hipEventRecord(v[n], h->stream));
+    ++n;
+    return LBM_OK;
+}
+
+int flush_timing(lbm *h)
+{
+    if (h->n_step_ev == 0 && h->n_wall_ev == 0) return LBM_OK;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (size_t i = 0; i + 1 < h->n_step_ev; i += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev_step[i], h->ev_step[i + 1]));
+        h->acc_step_ms += ms;
+        h->acc_step_n++;
+    }
+    for (size_t i = 0; i + 1 < h->n_wall_ev; i += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev_wall[i], h->ev_wall[i + 1]));
+        h->acc_wall_ms += ms;
+        h->acc_wall_n++;
+    }
+    h->n_step_ev = h->n_wall_ev = 0;
+    return LBM_OK;
+}
+
+int do_reduce(lbm *h)
+{
+    const bool odd_state = (h->step & 1) != 0;
+    const int cur = (int)(h->step & 1);
+    const int slot = h->reduce_count & 1;
+    int rc = LBM_DISPATCH(h, reduce, h, odd_state, cur, slot);
+    if (rc) return rc;
+    h->prev_reduce_step = h->last_reduce_step < 0 ? 0 : h->last_reduce_step;
+    h->last_reduce_step = h->step;
+    h->reduce_count++;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm_params_default(lbm_params_t *p)
+{
+    memset(p, 0, sizeof *p);
+    p->size = (int32_t)sizeof(lbm_params_t);
+    p->version = LBM_PARAMS_VERSION;
+    p->precision = LBM_F32;
+    p->flow = LBM_FLOW_CHANNEL;
+    p->scheme = LBM_WALL_SLIP_BB;
+    p->law = LBM_LAW_REICHARDT;
+    p->sa_on = 1;
+    p->plate_start = 0;
+    p->reduce_every = 100;
+    p->nu = 1e-3;
+    p->rho0 = 1.0;
+    p->u_ref = 1.0;
+    p->nut_init_ratio = 3.0;
+    p->kappa = 0.41;
+    p->B = 5.2;
+    p->beta = 0.28;
+    p->cb1 = 0.1355;
+    p->cb2 = 0.622;
+    p->sigma = 2.0 / 3.0;
+    p->cw2 = 0.3;
+    p->cw3 = 2.0;
+    p->cv1 = 7.1;
+    p->rlim = 10.0;
+}
+
+int64_t lbm_footprint(lbm_lattice_t lattice, int nx, int ny, int nz, const lbm_params_t *p)
+{
+    int rc = check_params(lattice, nx, ny, nz, p);
+    if (rc) return rc;
+    Layout L;
+    if (!make_layout((int)lattice, nx, ny, nz, p, &L)) return fail(LBM_EINVAL, "bad precision");
+    return L.total;
+}
+
+int lbm_create(lbm_lattice_t lattice, int nx, int ny, int nz, const lbm_params_t *p, void *dev_buf,
+               int64_t buf_bytes, void *stream, lbm_t **out)
+{
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_params(lattice, nx, ny, nz, p);
+    if (rc) return rc;
+    Layout L;
+    make_layout((int)lattice, nx, ny, nz, p, &L);
+    if (!dev_buf || buf_bytes < L.total)
+        return fail(LBM_EINVAL, "device buffer too small: %lld < %lld bytes", (long long)buf_bytes, (long long)L.total);
+    if (((uintptr_t)dev_buf & 255u) != 0) return fail(LBM_EINVAL, "device buffer must be 256-byte aligned");
+    lbm *h = new (std::nothrow) lbm();
+    if (!h) return fail(LBM_ENOMEM, "host allocation failed");
+    h->Q = (int)lattice;
+    h->D = lattice == LBM_D2Q9 ? 2 : 3;
+    h->nx = nx;
+    h->ny = ny;
+    h->nz = nz;
+    h->p = *p;
+    h->L = L;
+    h->base = (char *)dev_buf;
+    h->bytes = buf_bytes;
+    h->stream = (hipStream_t)stream;
+    h->timing = false;
+    h->n_step_ev = h->n_wall_ev = 0;
+    h->acc_step_ms = h->acc_wall_ms = 0.0;
+    h->acc_step_n = h->acc_wall_n = 0;
+    fill_kp(h);
+    rc = run_init(h, nullptr);
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_set_velocity(lbm_t *h, const double *u, int on_device)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    if (!u) return fail(LBM_EINVAL, "u is NULL");
+    const size_t bytes = (size_t)h->D * h->kp.ncell * sizeof(double);
+    const double *dev = u;
+    double *tmp = nullptr;
+    if (!on_device) {
+        HIPCHK(hipMalloc((void **)&tmp, bytes));
+        hipError_t e = hipMemcpyAsync(tmp, u, bytes, hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(tmp);
+            return fail(LBM_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
+        }
+        dev = tmp;
+    }
+    int rc = run_init(h, dev);
+    if (tmp) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return fail(LBM_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
+    return rc;
+}
+
+int lbm_set_wall_bc(lbm_t *h, lbm_wall_scheme_t scheme, double beta)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    if (scheme < LBM_WALL_FIXED_BB || scheme > LBM_WALL_HRFD) return fail(LBM_EINVAL, "unknown wall scheme");
+    if (scheme == LBM_WALL_HRFD && h->Q != 9) return fail(LBM_EINVAL, "HRFD is D2Q9 only");
+    h->p.scheme = scheme;
+    h->p.beta = beta;
+    h->kp.scheme = scheme;
+    h->kp.beta = beta;
+    // refresh the wall state for the new scheme from the current velocity
+    return LBM_DISPATCH(h, wall, h, (int)(h->step & 1));
+}
+
+int lbm_step(lbm_t *h, int64_t n)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    if (n < 0) return fail(LBM_EINVAL, "negative step count");
+    if (h->diverged) return fail(LBM_EDIVERGED, "the solution diverged at or before step %lld", (long long)h->last_reduce_step);
+    for (int64_t s = 0; s < n; ++s) {
+        const int64_t next = h->step + 1;
+        const bool odd = (next & 1) != 0;
+        const int rd = (int)(h->step & 1);
+        int rc;
+        if (h->timing && (rc = record(h, h->ev_step, h->n_step_ev))) return rc;
+        rc = LBM_DISPATCH(h, step, h, odd, rd);
+        if (rc) return rc;
+        if (h->timing && (rc = record(h, h->ev_step, h->n_step_ev))) return rc;
+        if (h->timing && (rc = record(h, h->ev_wall, h->n_wall_ev))) return rc;
+        rc = LBM_DISPATCH(h, wall, h, rd ^ 1);
+        if (rc) return rc;
+        if (h->timing && (rc = record(h, h->ev_wall, h->n_wall_ev))) return rc;
+        h->step = next;
+        if (h->p.reduce_every > 0 && h->step % h->p.reduce_every == 0) {
+            rc = do_reduce(h);
+            if (rc) return rc;
+        }
+        if (h->timing && h->n_step_ev >= 4096) {
+            rc = flush_timing(h);
+            if (rc) return rc;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_t *h, double *rho, double *u, double *nu_t, int on_device)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    const int64_t N = h->kp.ncell;
+    const bool odd_state = (h->step & 1) != 0;
+    const int cur = (int)(h->step & 1);
+    if (on_device) return LBM_DISPATCH(h, moments, h, odd_state, cur, rho, u, nu_t);
+    const size_t nb = (size_t)(N * (1 + h->D + 1)) * sizeof(double);
+    double *tmp = nullptr;
+    HIPCHK(hipMalloc((void **)&tmp, nb));
+    double *drho = rho ? tmp : nullptr, *du = u ? tmp + N : nullptr, *dn = nu_t ? tmp + N * (1 + h->D) : nullptr;
+    int rc = LBM_DISPATCH(h, moments, h, odd_state, cur, drho, du, dn);
+    hipError_t e = hipSuccess;
+    if (!rc && rho) e = hipMemcpyAsync(rho, drho, N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (!rc && e == hipSuccess && u) e = hipMemcpyAsync(u, du, (size_t)h->D * N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (!rc && e == hipSuccess && nu_t) e = hipMemcpyAsync(nu_t, dn, N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (rc) return rc;
+    if (e != hipSuccess || e2 != hipSuccess) return fail(LBM_EHIP, "moment copy failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    return LBM_OK;
+}
+
+int lbm_nu_tilde(lbm_t *h, double *nt, int on_device)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    if (!nt) return fail(LBM_EINVAL, "nt is NULL");
+    const int64_t N = h->kp.ncell;
+    const int cur = (int)(h->step & 1);
+    if (on_device) return LBM_DISPATCH(h, nt, h, cur, nt);
+    double *tmp = nullptr;
+    HIPCHK(hipMalloc((void **)&tmp, N * sizeof(double)));
+    int rc = LBM_DISPATCH(h, nt, h, cur, tmp);
+    hipError_t e = rc ? hipSuccess : hipMemcpyAsync(nt, tmp, N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (rc) return rc;
+    if (e != hipSuccess || e2 != hipSuccess) return fail(LBM_EHIP, "nu_tilde copy failed");
+    return LBM_OK;
+}
+
+int lbm_populations(lbm_t *h, double *f_host)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    if (!f_host) return fail(LBM_EINVAL, "f is NULL");
+    const size_t nb = (size_t)h->Q * h->kp.ncell * sizeof(double);
+    double *tmp = nullptr;
+    HIPCHK(hipMalloc((void **)&tmp, nb));
+    int rc = LBM_DISPATCH(h, pops, h, (h->step & 1) != 0, tmp);
+    hipError_t e = rc ? hipSuccess : hipMemcpyAsync(f_host, tmp, nb, hipMemcpyDeviceToHost, h->stream);
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (rc) return rc;
+    if (e != hipSuccess || e2 != hipSuccess) return fail(LBM_EHIP, "population copy failed");
+    return LBM_OK;
+}
+
+int lbm_wall(lbm_t *h, double *u_tau, double *cf, double *t, double *u_w, int64_t n)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    const int64_t nw = h->kp.nwall;
+    if (n < nw) return fail(LBM_EINVAL, "wall buffers hold %lld < %lld entries", (long long)n, (long long)nw);
+    if (nw == 0) return LBM_OK;
+    std::vector<double> ut(nw), td(3 * nw), uw(3 * nw);
+    HIPCHK(hipMemcpyAsync(ut.data(), h->kp.utau, nw * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(td.data(), h->kp.tdir, 3 * nw * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(uw.data(), h->kp.uw, 3 * nw * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int64_t w = 0; w < nw; ++w) {
+        if (u_tau) u_tau[w] = ut[w];
+        if (cf) cf[w] = 2.0 * (ut[w] / h->p.u_ref) * (ut[w] / h->p.u_ref);
+        for (int a = 0; a < 3; ++a) {
+            if (t) t[3 * w + a] = td[a * nw + w];
+            if (u_w) u_w[3 * w + a] = uw[a * nw + w];
+        }
+    }
+    return LBM_OK;
+}
+
+int64_t lbm_ncell(const lbm_t *h) { return h ? h->kp.ncell : -1; }
+int64_t lbm_nwall(const lbm_t *h) { return h ? h->kp.nwall : -1; }
+int64_t lbm_steps(const lbm_t *h) { return h ? h->step : -1; }
+
+int lbm_residual(lbm_t *h, lbm_residual_t *out)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    if (h->last_reduce_step != h->step) {
+        int rc = do_reduce(h);
+        if (rc) return rc;
+    }
+    double r[2 * NRED];
+    HIPCHK(hipMemcpyAsync(r, h->kp.result, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const int cur = (h->reduce_count - 1) & 1, prv = cur ^ 1;
+    const double *c = r + cur * NRED, *q = r + prv * NRED;
+    memset(out, 0, sizeof *out);
+    out->step = h->step;
+    out->steps_since_previous = h->last_reduce_step - h->prev_reduce_step;
+    out->mass = (double)h->kp.ncell * h->p.rho0 + c[0];
+    for (int a = 0; a < 3; ++a) out->momentum[a] = c[1 + a];
+    const double K = out->steps_since_previous > 0 ? (double)out->steps_since_previous : 1.0;
+    out->l2_du_rel = c[5] > 0.0 ? sqrt(c[4]) / (K * sqrt(c[5])) : 0.0;
+    const double nw = h->kp.nwall > 0 ? (double)h->kp.nwall : 1.0;
+    out->mean_u_tau = c[7] / nw;
+    const double prev = q[7] / nw;
+    out->d_u_tau_rel = (h->reduce_count >= 2 && prev > 0.0) ? fabs(out->mean_u_tau - prev) / prev : 0.0;
+    out->nan_flag = c[6] > 0.0 || !isfinite(c[4]) || !isfinite(c[5]) ? 1.0 : 0.0;
+    if (out->nan_flag != 0.0) {
+        h->diverged = true;
+        return fail(LBM_EDIVERGED, "divergence detected at step %lld", (long long)h->step);
+    }
+    return LBM_OK;
+}
+
+int lbm_set_timing(lbm_t *h, int on)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    int rc = flush_timing(h);
+    if (rc) return rc;
+    h->timing = on != 0;
+    h->acc_step_ms = h->acc_wall_ms = 0.0;
+    h->acc_step_n = h->acc_wall_n = 0;
+    return LBM_OK;
+}
+
+int lbm_get_timing(lbm_t *h, lbm_timing_t *out)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    int rc = flush_timing(h);
+    if (rc) return rc;
+    out->step_launches = h->acc_step_n;
+    out->step_ms = h->acc_step_ms;
+    out->wall_launches = h->acc_wall_n;
+    out->wall_ms = h->acc_wall_ms;
+    return LBM_OK;
+}
+
+int64_t lbm_checkpoint_bytes(const lbm_t *h)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    return 64 + h->L.total;
+}
+
+int lbm_save(lbm_t *h, void *host, int64_t bytes)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    if (!host || bytes < 64 + h->L.total) return fail(LBM_EINVAL, "checkpoint buffer too small");
+    int64_t hdr[8] = {0x4c424d434b505431LL, h->Q, h->nx, h->ny, h->nz, h->step, h->L.total, h->p.precision};
+    memcpy(host, hdr, sizeof hdr);
+    HIPCHK(hipMemcpyAsync((char *)host + 64, h->base, h->L.total, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int lbm_load(lbm_t *h, const void *host, int64_t bytes)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    if (!host || bytes < 64 + h->L.total) return fail(LBM_EINVAL, "checkpoint buffer too small");
+    int64_t hdr[8];
+    memcpy(hdr, host, sizeof hdr);
+    if (hdr[0] != 0x4c424d434b505431LL || hdr[1] != h->Q || hdr[2] != h->nx || hdr[3] != h->ny || hdr[4] != h->nz ||
+        hdr[6] != h->L.total || hdr[7] != h->p.precision)
+        return fail(LBM_EINVAL, "checkpoint does not match this lattice");
+    HIPCHK(hipMemcpyAsync(h->base, (const char *)host + 64, h->L.total, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->step = hdr[5];
+    h->last_reduce_step = -1;
+    h->prev_reduce_step = h->step;
+    h->reduce_count = 0;
+    h->diverged = false;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_t *h)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    (void)hipStreamSynchronize(h->stream);
+    for (hipEvent_t e : h->ev_step) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->ev_wall) (void)hipEventDestroy(e);
+    delete h;
+    return LBM_OK;
+}
+
+const char *lbm_last_error(void) { return g_err; }
+
+}  // extern "C"

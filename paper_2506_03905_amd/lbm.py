@@ -1,0 +1,252 @@
+"""ctypes binding of ``liblbm.so`` (C ABI: ``include/lbm.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels.
+PyTorch supplies the device buffer and the stream.  The library is loaded on
+first use; if it is missing the call raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EDIVERGED, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_D2Q9, LBM_D3Q19 = 9, 19
+LBM_F64, LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2, 3
+LBM_FLOW_CHANNEL, LBM_FLOW_PLATE = 0, 1
+LBM_WALL_FIXED_BB, LBM_WALL_SLIP_BB, LBM_WALL_HRFD = 0, 1, 2
+LBM_LAW_REICHARDT, LBM_LAW_SA = 0, 1
+LBM_COLL_BGK, LBM_COLL_CM = 0, 1
+
+PRECISION = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
+SCHEME = {"fixed_bb": LBM_WALL_FIXED_BB, "slip_bb": LBM_WALL_SLIP_BB, "hrfd": LBM_WALL_HRFD}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+class lbm_params_t(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_int32), ("version", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("flow", ctypes.c_int32), ("scheme", ctypes.c_int32), ("law", ctypes.c_int32),
+        ("sa_on", ctypes.c_int32), ("plate_start", ctypes.c_int32),
+        ("reduce_every", ctypes.c_int32), ("collision", ctypes.c_int32),
+        ("nu", ctypes.c_double), ("rho0", ctypes.c_double), ("force", ctypes.c_double * 3),
+        ("u_init", ctypes.c_double * 3), ("u_inlet", ctypes.c_double), ("u_ref", ctypes.c_double),
+        ("wall_u_bottom", ctypes.c_double * 3), ("wall_u_top", ctypes.c_double * 3),
+        ("nut_init_ratio", ctypes.c_double), ("kappa", ctypes.c_double), ("B", ctypes.c_double),
+        ("beta", ctypes.c_double), ("cb1", ctypes.c_double), ("cb2", ctypes.c_double),
+        ("sigma", ctypes.c_double), ("cw2", ctypes.c_double), ("cw3", ctypes.c_double),
+        ("cv1", ctypes.c_double), ("rlim", ctypes.c_double),
+    ]
+
+
+class lbm_residual_t(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("steps_since_previous", ctypes.c_int64),
+        ("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3),
+        ("l2_du_rel", ctypes.c_double), ("mean_u_tau", ctypes.c_double),
+        ("d_u_tau_rel", ctypes.c_double), ("nan_flag", ctypes.c_double),
+    ]
+
+
+class lbm_timing_t(ctypes.Structure):
+    _fields_ = [
+        ("step_launches", ctypes.c_int64), ("step_ms", ctypes.c_double),
+        ("wall_launches", ctypes.c_int64), ("wall_ms", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first "
+                           "(python -m paper_2506_03905_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    P = ctypes.POINTER(lbm_params_t)
+    sig = {
+        "lbm_params_default": (None, [P]),
+        "lbm_footprint": (i64, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]),
+        "lbm_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P,
+                                      vp, i64, vp, ctypes.POINTER(vp)]),
+        "lbm_set_velocity": (ctypes.c_int, [vp, vp, ctypes.c_int]),
+        "lbm_set_wall_bc": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_double]),
+        "lbm_step": (ctypes.c_int, [vp, i64]),
+        "lbm_moments": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int]),
+        "lbm_nu_tilde": (ctypes.c_int, [vp, vp, ctypes.c_int]),
+        "lbm_populations": (ctypes.c_int, [vp, vp]),
+        "lbm_wall": (ctypes.c_int, [vp, vp, vp, vp, vp, i64]),
+        "lbm_ncell": (i64, [vp]),
+        "lbm_nwall": (i64, [vp]),
+        "lbm_steps": (i64, [vp]),
+        "lbm_residual": (ctypes.c_int, [vp, ctypes.POINTER(lbm_residual_t)]),
+        "lbm_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
+        "lbm_get_timing": (ctypes.c_int, [vp, ctypes.POINTER(lbm_timing_t)]),
+        "lbm_checkpoint_bytes": (i64, [vp]),
+        "lbm_save": (ctypes.c_int, [vp, vp, i64]),
+        "lbm_load": (ctypes.c_int, [vp, vp, i64]),
+        "lbm_destroy": (ctypes.c_int, [vp]),
+        "lbm_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _ = dp
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != LBM_OK:
+        raise LbmError(rc, lib().lbm_last_error().decode())
+
+
+def lbm_params_default(**overrides) -> lbm_params_t:
+    p = lbm_params_t()
+    lib().lbm_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        if k in ("force", "u_init", "wall_u_bottom", "wall_u_top"):
+            arr = getattr(p, k)
+            for a in range(3):
+                arr[a] = float(v[a]) if a < len(v) else 0.0
+        else:
+            if not hasattr(p, k):
+                raise AttributeError(k)
+            setattr(p, k, v)
+    return p
+
+
+def lbm_footprint(lattice: int, nx: int, ny: int, nz: int, p: lbm_params_t) -> int:
+    n = lib().lbm_footprint(lattice, nx, ny, nz, ctypes.byref(p))
+    if n < 0:
+        _check(int(n))
+    return int(n)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Lattice:
+    """One lattice resident in a caller-owned device buffer (a torch tensor)."""
+
+    def __init__(self, lattice: int, nx: int, ny: int, nz: int, p: lbm_params_t,
+                 device="cuda", stream=None, buffer=None):
+        import torch
+
+        self.lattice, self.nx, self.ny, self.nz = lattice, nx, ny, nz
+        self.D = 2 if lattice == LBM_D2Q9 else 3
+        self.p = p
+        self.bytes = lbm_footprint(lattice, nx, ny, nz, p)
+        if buffer is None:
+            buffer = torch.empty(self.bytes + 256, dtype=torch.uint8, device=device)
+        self.buffer = buffer  # keeps the device memory alive
+        base = buffer.data_ptr()
+        aligned = (base + 255) & ~255
+        avail = buffer.numel() - (aligned - base)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(buffer.device)
+        h = ctypes.c_void_p()
+        _check(lib().lbm_create(lattice, nx, ny, nz, ctypes.byref(p), ctypes.c_void_p(aligned),
+                                avail, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.ncell = int(lib().lbm_ncell(h))
+        self.nwall = int(lib().lbm_nwall(h))
+        self.shape = (nz, ny, nx)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- C ABI with the same names -----------------------------------------
+    def lbm_set_velocity(self, u: np.ndarray):
+        u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(self.D, -1))
+        if u.shape[1] != self.ncell:
+            raise ValueError("velocity field has the wrong size")
+        _check(lib().lbm_set_velocity(self.h, _ptr(u), 0))
+
+    def lbm_set_wall_bc(self, scheme: int, beta: float = 0.28):
+        _check(lib().lbm_set_wall_bc(self.h, scheme, beta))
+
+    def lbm_step(self, n: int = 1):
+        _check(lib().lbm_step(self.h, n))
+
+    def lbm_moments(self):
+        rho = np.zeros(self.ncell)
+        u = np.zeros(self.D * self.ncell)
+        nut = np.zeros(self.ncell)
+        _check(lib().lbm_moments(self.h, _ptr(rho), _ptr(u), _ptr(nut), 0))
+        return (rho.reshape(self.shape), u.reshape((self.D,) + self.shape),
+                nut.reshape(self.shape))
+
+    def lbm_nu_tilde(self):
+        nt = np.zeros(self.ncell)
+        _check(lib().lbm_nu_tilde(self.h, _ptr(nt), 0))
+        return nt.reshape(self.shape)
+
+    def lbm_populations(self):
+        f = np.zeros(self.lattice * self.ncell)
+        _check(lib().lbm_populations(self.h, _ptr(f)))
+        return f.reshape((self.lattice,) + self.shape)
+
+    def lbm_wall(self):
+        nw = self.nwall
+        ut, cf = np.zeros(nw), np.zeros(nw)
+        t, uw = np.zeros((nw, 3)), np.zeros((nw, 3))
+        _check(lib().lbm_wall(self.h, _ptr(ut), _ptr(cf), _ptr(t), _ptr(uw), nw))
+        return {"utau": ut, "cf": cf, "t": t, "uw": uw}
+
+    def lbm_residual(self) -> dict:
+        r = lbm_residual_t()
+        rc = lib().lbm_residual(self.h, ctypes.byref(r))
+        out = {"step": r.step, "steps_since_previous": r.steps_since_previous, "mass": r.mass,
+               "momentum": list(r.momentum), "l2_du_rel": r.l2_du_rel,
+               "mean_u_tau": r.mean_u_tau, "d_u_tau_rel": r.d_u_tau_rel, "nan_flag": r.nan_flag,
+               "rc": rc}
+        if rc not in (LBM_OK, LBM_EDIVERGED):
+            _check(rc)
+        return out
+
+    def lbm_set_timing(self, on: bool):
+        _check(lib().lbm_set_timing(self.h, 1 if on else 0))
+
+    def lbm_get_timing(self) -> dict:
+        t = lbm_timing_t()
+        _check(lib().lbm_get_timing(self.h, ctypes.byref(t)))
+        return {"step_launches": t.step_launches, "step_ms": t.step_ms,
+                "wall_launches": t.wall_launches, "wall_ms": t.wall_ms}
+
+    def lbm_save(self) -> bytes:
+        n = int(lib().lbm_checkpoint_bytes(self.h))
+        buf = ctypes.create_string_buffer(n)
+        _check(lib().lbm_save(self.h, buf, n))
+        return buf.raw
+
+    def lbm_load(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(lib().lbm_load(self.h, buf, len(blob)))
+
+    @property
+    def steps(self) -> int:
+        return int(lib().lbm_steps(self.h))

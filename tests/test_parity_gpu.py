@@ -1,0 +1,326 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+FP64 storage is compared element by element; FP32 / FP16 / BF16 storage by
+relative L2 error.  Inputs come from the seeded generators in
+paper_2506_03905_amd.inputs and are handed to both sides.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2506_03905_amd import inputs, units
+
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_2506_03905_amd.lbm")
+
+
+def _torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _pair(q, nx, ny, nz, *, scheme, u0, nu, force=(0, 0, 0), flow=O.CHANNEL, plate_start=0,
+          u_inlet=0.0, sa_on=1, law=O.REICHARDT, beta=0.28, precision="f64",
+          wall_u_top=(0, 0, 0), collision=O.BGK, oracle_shape=None, oracle_u0=None):
+    _torch_gpu()
+    oq = dict(nx=nx, ny=ny, nz=nz)
+    if oracle_shape is not None:
+        oq = dict(zip(("nx", "ny", "nz"), oracle_shape))
+    op = O.params(q=q, **oq, flow=flow, scheme=scheme, law=law, sa_on=sa_on,
+                  plate_start=plate_start, nu=nu, force=force, u_inlet=u_inlet, beta=beta,
+                  wall_u_top=wall_u_top, collision=collision)
+    o = O.Oracle(op, u0 if oracle_u0 is None else oracle_u0)
+    gp = L.lbm_params_default(precision=L.PRECISION[precision], flow=flow, scheme=scheme,
+                              law=law, sa_on=sa_on, plate_start=plate_start, nu=nu,
+                              force=force, u_inlet=u_inlet, beta=beta, wall_u_top=wall_u_top,
+                              reduce_every=0, collision=collision)
+    g = L.Lattice(q, nx, ny, nz, gp)
+    g.lbm_set_velocity(u0)
+    return o, g
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _compare_f64(o, g, tol=1e-11):
+    rho_g, u_g, nut_g = g.lbm_moments()
+    assert _rel(u_g, o.u()) < tol, _rel(u_g, o.u())
+    assert np.abs(rho_g - o.rho()).max() < tol
+    if o.p.sa_on:
+        assert _rel(g.lbm_nu_tilde(), o.nt()) < tol
+        assert _rel(nut_g, o.nut()) < tol
+    wg, wo = g.lbm_wall(), o.wall()
+    if o.nwall:
+        assert _rel(wg["utau"], wo["utau"]) < tol
+        assert _rel(wg["uw"], wo["uw"]) < max(tol, 1e-12)
+
+
+def _channel_u0(q, nx, ny, nz, ub, amp=1e-3, seed=0):
+    D = 2 if q == 9 else 3
+    return inputs.channel_velocity(seed, D, nz, ny, nx, ub, amp)
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 10, 51])
+def test_d2q9_channel_slip_bb_f64(steps):
+    lat = units.channel(2000.0, 8)
+    nx, ny = 4, 16
+    u0 = _channel_u0(9, nx, ny, 1, lat["u_bulk"])
+    o, g = _pair(9, nx, ny, 1, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"] * 20, 0, 0))
+    o.step(steps)
+    g.lbm_step(steps)
+    _compare_f64(o, g)
+
+
+@pytest.mark.parametrize("law", [O.REICHARDT, O.SA_LAW])
+def test_d2q9_channel_hrfd_f64(law):
+    lat = units.channel(4200.0, 10)
+    nx, ny = 6, 20
+    u0 = _channel_u0(9, nx, ny, 1, lat["u_bulk"])
+    o, g = _pair(9, nx, ny, 1, scheme=O.HRFD, u0=u0, nu=lat["nu"], law=law,
+                 force=(lat["force"], 0, 0))
+    o.step(40)
+    g.lbm_step(40)
+    _compare_f64(o, g)
+
+
+def test_d2q9_poiseuille_fixed_bb_f64():
+    tau, H = 0.8, 16
+    nu = (tau - 0.5) / 3
+    g_ = 8 * nu * 1e-3 / H ** 2
+    u0 = np.zeros((2, 1, H, 3))
+    o, g = _pair(9, 3, H, 1, scheme=O.BB_FIXED, u0=u0, nu=nu, force=(g_, 0, 0), sa_on=0,
+                 wall_u_top=(0.002, 0, 0))
+    o.step(333)
+    g.lbm_step(333)
+    _compare_f64(o, g)
+
+
+@pytest.mark.parametrize("steps", [1, 2, 25])
+def test_d3q19_channel_slip_bb_f64(steps):
+    lat = units.channel(5000.0, 6)
+    nx, ny, nz = 5, 12, 4
+    u0 = _channel_u0(19, nx, ny, nz, lat["u_bulk"])
+    o, g = _pair(19, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"] * 10, 0, 0))
+    o.step(steps)
+    g.lbm_step(steps)
+    _compare_f64(o, g)
+
+
+@pytest.mark.parametrize("scheme", [O.BB_SLIP, O.HRFD])
+@pytest.mark.parametrize("steps", [1, 2, 60])
+def test_d2q9_plate_f64(scheme, steps):
+    nx, ny, U = 300, 12, 0.05
+    u0 = inputs.channel_velocity(3, 2, 1, ny, nx, U, 1e-3)
+    o, g = _pair(9, nx, ny, 1, scheme=scheme, u0=u0, nu=0.03, flow=O.PLATE, plate_start=40,
+                 u_inlet=U)
+    o.step(steps)
+    g.lbm_step(steps)
+    _compare_f64(o, g)
+
+
+def test_populations_export_matches_oracle():
+    lat = units.channel(2000.0, 8)
+    nx, ny = 4, 16
+    u0 = _channel_u0(9, nx, ny, 1, lat["u_bulk"])
+    o, g = _pair(9, nx, ny, 1, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"])
+    for n in (1, 1, 5):  # odd layout, even layout, odd layout
+        o.step(n)
+        g.lbm_step(n)
+        assert np.abs(g.lbm_populations() - o.f()).max() < 1e-13
+
+
+def test_residual_reduction_matches_oracle_definition():
+    lat = units.channel(2000.0, 8)
+    nx, ny = 4, 16
+    u0 = _channel_u0(9, nx, ny, 1, lat["u_bulk"])
+    o, g = _pair(9, nx, ny, 1, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"])
+    r0 = g.lbm_residual()
+    o.step(20)
+    g.lbm_step(20)
+    r = g.lbm_residual()
+    uo0 = u0.reshape(2, -1)
+    uo = o.u().reshape(2, -1)
+    tot = o.totals()
+    assert abs(r["mass"] - tot[0]) < 1e-12 * tot[0]
+    assert np.allclose(r["momentum"][:2], tot[1:3], rtol=1e-11, atol=1e-18)
+    l2 = np.linalg.norm(uo - uo0) / (20 * np.linalg.norm(uo))
+    assert abs(r["l2_du_rel"] / l2 - 1) < 1e-9
+    assert abs(r["mean_u_tau"] / o.wall()["utau"].mean() - 1) < 1e-12
+    assert r["nan_flag"] == 0.0 and r0["step"] == 0 and r["steps_since_previous"] == 20
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f16", 1e-2), ("bf16", 5e-2)])
+def test_d3q19_channel_reduced_precision(precision, tol):
+    lat = units.channel(5000.0, 12)
+    nx, ny, nz = 16, 24, 8
+    u0 = _channel_u0(19, nx, ny, nz, lat["u_bulk"])
+    o, g = _pair(19, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"], 0, 0), precision=precision)
+    o.step(100)
+    g.lbm_step(100)
+    _, ug, _ = g.lbm_moments()
+    uo = o.u()
+    err = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    assert err < tol, err
+    ut_err = np.linalg.norm(g.lbm_wall()["utau"] - o.wall()["utau"]) / np.linalg.norm(o.wall()["utau"])
+    assert ut_err < tol, ut_err
+
+
+def test_checkpoint_roundtrip_bitwise():
+    lat = units.channel(2000.0, 8)
+    nx, ny = 4, 16
+    u0 = _channel_u0(9, nx, ny, 1, lat["u_bulk"])
+    _, g = _pair(9, nx, ny, 1, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"], precision="f32")
+    _, h = _pair(9, nx, ny, 1, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"], precision="f32")
+    g.lbm_step(7)
+    blob = g.lbm_save()
+    g.lbm_step(9)
+    h.lbm_load(blob)
+    h.lbm_step(9)
+    assert np.array_equal(g.lbm_moments()[1], h.lbm_moments()[1])
+    assert np.array_equal(g.lbm_populations(), h.lbm_populations())
+
+
+def test_divergence_is_reported():
+    _torch_gpu()
+    p = L.lbm_params_default(precision=L.LBM_F64, scheme=L.LBM_WALL_FIXED_BB, sa_on=0, nu=1e-3,
+                             reduce_every=0)
+    g = L.Lattice(9, 4, 8, 1, p)
+    u = np.zeros((2, 1, 8, 4))
+    u[0, 0, 3, 1] = np.nan
+    g.lbm_set_velocity(u)
+    g.lbm_step(2)
+    r = g.lbm_residual()
+    assert r["rc"] == L.LBM_EDIVERGED and r["nan_flag"] == 1.0
+    with pytest.raises(L.LbmError):
+        g.lbm_step(1)
+
+
+# ------------------------------------------------- central-moment collision ---
+@pytest.mark.parametrize("steps", [1, 2, 31])
+def test_d2q9_channel_cm_f64(steps):
+    lat = units.channel(2000.0, 8)
+    nx, ny = 4, 16
+    u0 = _channel_u0(9, nx, ny, 1, lat["u_bulk"])
+    o, g = _pair(9, nx, ny, 1, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"] * 20, 0, 0), collision=O.CM)
+    o.step(steps)
+    g.lbm_step(steps)
+    _compare_f64(o, g)
+
+
+@pytest.mark.parametrize("steps", [1, 2, 20])
+def test_d3q19_channel_cm_f64(steps):
+    lat = units.channel(5000.0, 6)
+    nx, ny, nz = 5, 12, 4
+    u0 = _channel_u0(19, nx, ny, nz, lat["u_bulk"])
+    o, g = _pair(19, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"] * 10, 0, 0), collision=O.CM)
+    o.step(steps)
+    g.lbm_step(steps)
+    _compare_f64(o, g)
+
+
+@pytest.mark.parametrize("scheme", [O.BB_SLIP, O.HRFD])
+def test_d2q9_plate_cm_low_viscosity_f64(scheme):
+    """The plate at the viscosity of the 2048 x 256 workload (tau - 1/2 = 6e-5)."""
+    nx, ny, U = 260, 24, 0.1
+    u0 = inputs.channel_velocity(5, 2, 1, ny, nx, U, 0.0)
+    o, g = _pair(9, nx, ny, 1, scheme=scheme, u0=u0, nu=1.984e-5, flow=O.PLATE,
+                 plate_start=16, u_inlet=U, collision=O.CM)
+    o.step(150)
+    g.lbm_step(150)
+    _compare_f64(o, g, tol=1e-10)
+
+
+# ------------------------------------------------------ configuration cases ---
+def _cfg1(collision):
+    lat = units.channel(2000.0, 32, 0.05)
+    nx, ny = 4, 64
+    u0 = inputs.channel_velocity(0, 2, 1, ny, nx, 0.0, 1e-3)
+    return _pair(9, nx, ny, 1, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"], 0, 0), collision=collision)
+
+
+def test_config1_bgk_parity_then_divergence():
+    """D2Q9 4 x 64 channel, FP64, BGK, rest + seeded 1e-3 perturbation: parity
+    element-wise while the run is finite; BGK with slip-velocity bounce-back
+    then diverges near step 1450 on both sides, and the GPU reduction says so."""
+    o, g = _cfg1(O.BGK)
+    o.step(1000)
+    g.lbm_step(1000)
+    _compare_f64(o, g, tol=1e-9)
+    o.step(2000)
+    g.lbm_step(2000)
+    assert not np.all(np.isfinite(o.u()))
+    assert g.lbm_residual()["rc"] == L.LBM_EDIVERGED
+
+
+def test_config1_cm_full_run_parity():
+    """The same workload with the paper's central-moment collision: 20000
+    steps, element-wise FP64 parity at the end."""
+    o, g = _cfg1(O.CM)
+    for _ in range(4):
+        o.step(5000)
+        g.lbm_step(5000)
+    _compare_f64(o, g, tol=1e-9)
+    assert g.lbm_residual()["nan_flag"] == 0.0
+
+
+def _invariant_channel(q, nx, ny, nz, precision, steps, collision=O.BGK):
+    lat = units.channel(5000.0, ny // 2, 0.05)
+    D = 2 if q == 9 else 3
+    u0 = inputs.channel_velocity(0, D, nz, ny, nx, lat["u_bulk"], 0.0)
+    u0c = inputs.channel_velocity(0, D, 1, ny, 1, lat["u_bulk"], 0.0)
+    o, g = _pair(q, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"], 0, 0), precision=precision, collision=collision,
+                 oracle_shape=(1, ny, 1), oracle_u0=u0c)
+    del u0
+    o.step(steps)
+    g.lbm_step(steps)
+    _, ug, _ = g.lbm_moments()
+    uo = o.u()[:, 0, :, 0]
+    # every (x, z) column computes the same arithmetic: bitwise identical
+    assert np.array_equal(ug, np.broadcast_to(ug[:, :1, :, :1], ug.shape))
+    col = ug[:, 0, :, 0]
+    err = np.linalg.norm(col - uo) / np.linalg.norm(uo)
+    ut_g, ut_o = g.lbm_wall()["utau"], o.wall()["utau"]
+    ut_err = abs(ut_g.mean() - ut_o.mean()) / ut_o.mean()
+    return err, ut_err
+
+
+def test_config3_full_size_invariance_f32():
+    """512 x 256 x 256 D3Q19 FP32 (the benchmark's lattice and launch) from the
+    Dean start: x/z-invariant, and equal to the oracle's single column."""
+    err, ut_err = _invariant_channel(19, 512, 256, 256, "f32", 200)
+    assert err < 1e-4 and ut_err < 1e-4, (err, ut_err)
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f16", 1e-3), ("bf16", 1e-2)])
+def test_config4_full_size_precision(precision, tol):
+    """768 x 384 x 384 D3Q19 with FP32/FP16/BF16 storage against the FP64
+    oracle column (relative L2 of u and of u_tau)."""
+    err, ut_err = _invariant_channel(19, 768, 384, 384, precision, 100)
+    assert err < tol and ut_err < tol, (err, ut_err)
+
+
+@pytest.mark.parametrize("scheme", [O.BB_SLIP, O.HRFD])
+def test_config2_full_size_plate_f64(scheme):
+    """2048 x 256 flat plate, CM collision, 64-cell slip leading section,
+    U = 0.1, Re = 5e6 per L_ref = 992 cells: FP64 parity after 40 steps."""
+    nx, ny, U = 2048, 256, 0.1
+    nu = U * 992 / 5e6
+    u0 = inputs.channel_velocity(0, 2, 1, ny, nx, U, 0.0)
+    o, g = _pair(9, nx, ny, 1, scheme=scheme, u0=u0, nu=nu, flow=O.PLATE, plate_start=64,
+                 u_inlet=U, collision=O.CM)
+    o.step(40)
+    g.lbm_step(40)
+    _compare_f64(o, g, tol=1e-10)
