@@ -26,13 +26,16 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
-def bytes_per_lup(q: int, precision: str) -> int:
+def bytes_per_lup(q: int, precision: str, sa: bool = True) -> int:
     """Algorithmic bytes per lattice update: every population read and written
     once, nu_tilde read and written once, the velocity written once and read
-    once through the SA stencil."""
+    once through the SA stencil (without SA: populations and the velocity
+    written once)."""
     sb = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[precision]
     tb = 8 if precision == "f64" else 4
     D = 2 if q == 9 else 3
+    if not sa:
+        return 2 * q * sb + D * tb
     return 2 * q * sb + 2 * tb + 2 * D * tb
 
 
@@ -70,6 +73,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--collision", default="bgk", choices=["bgk", "cm"])
     ap.add_argument("--amp", type=float, default=0.0)
+    ap.add_argument("--sa", default="on", choices=["on", "off"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -104,7 +108,7 @@ def main():
     coll = {"bgk": L.LBM_COLL_BGK, "cm": L.LBM_COLL_CM}[args.collision]
     p = L.lbm_params_default(precision=L.PRECISION[args.precision], scheme=L.LBM_WALL_SLIP_BB,
                              nu=lat["nu"], force=(lat["force"], 0, 0), u_ref=lat["u_bulk"],
-                             reduce_every=100, collision=coll)
+                             reduce_every=100, collision=coll, sa_on=1 if args.sa == "on" else 0)
     g = L.Lattice(L.LBM_D3Q19, nx, ny, nz, p, device="cuda:0")
     u0 = inputs.channel_velocity(0, 3, nz, ny, nx, lat["u_bulk"], args.amp)
     g.lbm_set_velocity(u0)
@@ -129,7 +133,7 @@ def main():
     res = g.lbm_residual()
     ncell = nx * ny * nz
     mlups = ncell * args.steps / (ms * 1e-3) / 1e6
-    bpl = bytes_per_lup(19, args.precision)
+    bpl = bytes_per_lup(19, args.precision, args.sa == "on")
     k_ms = tm["step_ms"] / max(tm["step_launches"], 1)
     achieved = bpl * ncell / (k_ms * 1e-3) / 1e9
     out = {
@@ -147,7 +151,8 @@ def main():
                   "f64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"3-D channel D3Q19 {nx}x{ny}x{nz}, Re_tau 5000, "
-                               f"{args.collision.upper()} + SA, slip-velocity bounce-back "
+                               f"{args.collision.upper()}" + (" + SA" if args.sa == "on" else
+                                                               " (no SA)") + ", slip-velocity bounce-back "
                                f"(Reichardt), Dean start" + (f" + {args.amp:g} perturbation"
                                                              if args.amp else ""),
                    "cells": ncell, "collision": args.collision, "parallelism": "single GPU"},

@@ -128,6 +128,8 @@ typedef struct lbm_params {
     double kappa, B;         /* von Karman constant (also the SA kappa), log-law intercept */
     double beta;             /* HRFD blending parameter (eq. 27) */
     double cb1, cb2, sigma, cw2, cw3, cv1, rlim; /* SA constants (after eq. 14) */
+    double store_shift_u; /* populations are stored as f - f_eq(rho0, (store_shift_u, 0, 0));
+                             0 (default) stores f - w rho0 */
 } lbm_params_t;
 
 /* Reduction result (all double).  mass = sum rho, momentum = sum rho u over all
@@ -231,6 +233,63 @@ int lbm_load(lbm_t *h, const void *host, int64_t bytes);
 /* Releases the handle's host state and events; the device buffer stays the
  * caller's. */
 int lbm_destroy(lbm_t *h);
+
+/* ---------------------------------------------------------------------------
+ * Serving pool: many independent solves resident in one device buffer.
+ *
+ * Requests are admitted by footprint (first fit in the pool buffer) and
+ * advanced together.  Small D2Q9 lattices (<= 65536 cells; plates with
+ * ny <= 256) are advanced by one persistent launch in which each lattice is
+ * owned by one workgroup that loops over the steps; larger lattices run the
+ * regular kernels on a second stream, so both kinds overlap on the device.
+ * Every lattice stops on convergence (residual of lbm_residual_t below `tol`
+ * at a reduction step), divergence or `max_steps`.  Results of one lattice do
+ * not depend on what else is resident.
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_pool lbm_pool_t;
+
+enum { LBM_SLOT_IDLE = 0, LBM_SLOT_RUNNING = 1, LBM_SLOT_CONVERGED = 2, LBM_SLOT_CAPPED = 3, LBM_SLOT_DIVERGED = 4 };
+
+typedef struct lbm_pool_status {
+    int32_t status;     /* LBM_SLOT_* */
+    int32_t batched;    /* 1: advanced by the persistent small-lattice launch */
+    int64_t steps;      /* steps taken */
+    double residual;    /* last residual ||u^n - u^(n-K)|| / (K ||u^n||) */
+    double mean_u_tau;  /* mean u_tau over the wall cells at the last residual */
+    int64_t footprint;  /* bytes of the pool buffer held by the slot */
+} lbm_pool_status_t;
+
+/* dev_buf: caller-owned device memory (256-byte aligned) of `bytes`; the first
+ * max_slots descriptors live at its start.  `stream` carries the small-lattice
+ * launches; the pool creates one more (default-priority) stream. */
+int lbm_pool_create(void *dev_buf, int64_t bytes, int max_slots, void *stream, lbm_pool_t **out);
+
+/* Largest contiguous free block (bytes). */
+int64_t lbm_pool_free_bytes(const lbm_pool_t *pool);
+
+/* Admits one solve: the lattice is created in the pool buffer and initialized
+ * (optionally from a host velocity field, as lbm_set_velocity).  Returns
+ * LBM_ENOMEM (nothing changed) if no slot or no block of lbm_footprint()
+ * bytes is free.  *slot receives the slot index. */
+int lbm_pool_admit(lbm_pool_t *pool, lbm_lattice_t lattice, int nx, int ny, int nz, const lbm_params_t *p,
+                   const double *u0_host, double tol, int64_t max_steps, int *slot);
+
+/* Advances every running slot by up to `steps` steps and synchronizes. */
+int lbm_pool_step(lbm_pool_t *pool, int64_t steps);
+
+/* Status of one slot (host data refreshed by lbm_pool_step). */
+int lbm_pool_poll(lbm_pool_t *pool, int slot, lbm_pool_status_t *out);
+
+/* The slot's lattice handle, for lbm_moments / lbm_wall / lbm_populations
+ * (valid until lbm_pool_release); NULL for a bad slot. */
+lbm_t *lbm_pool_lattice(lbm_pool_t *pool, int slot);
+
+/* Frees the slot and its memory (synchronizes). */
+int lbm_pool_release(lbm_pool_t *pool, int slot);
+
+/* Releases every slot and the pool's host state and stream; the buffer stays
+ * the caller's. */
+int lbm_pool_destroy(lbm_pool_t *pool);
 
 /* Thread-local message describing the last error (empty if none). */
 const char *lbm_last_error(void);

@@ -27,6 +27,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
 #include <new>
 #include <vector>
 
@@ -38,6 +39,9 @@ using namespace lbmd;
 namespace {
 
 constexpr int BLK = 256;
+#ifndef LBM_ROWMAP
+#define LBM_ROWMAP 1
+#endif
 constexpr int NRED = 8;        // reduction slots
 constexpr int RED_BLOCKS = 2048;
 
@@ -59,56 +63,57 @@ __device__ __forceinline__ int64_t xcd_block(uint32_t b, uint32_t nb)
 template <typename T> __device__ __forceinline__ T clamp0(T v) { return v > (T)0 ? v : (T)0; }
 
 // ---------------------------------------------------------------------------
-// k_step: one fused LBM-RANS step.
-// rd: ping-pong index of u^{n-1} / nu_tilde^n; results go to rd ^ 1.
+// Per-cell context: coordinates, neighbour offsets (periodic in x for the
+// channel and in z), wall index.
 // ---------------------------------------------------------------------------
-template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC>
-__global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
-{
-    constexpr int D = Lat<Q>::D;
-    using SS = Stor<S>;
-    const int nx = P.nx, ny = P.ny, nz = P.nz;
-    const int64_t N = P.ncell;
-    const int tid = threadIdx.x;
-
+struct Cell {
     int x, y, z;
-    int64_t cell;
-    bool active;
-    if (!PLATE) {
-        cell = xcd_block(blockIdx.x, gridDim.x) * BLK + tid;
-        active = cell < N;
-        int64_t r = cell / nx;
-        x = (int)(cell - r * nx);
-        y = (int)(r % ny);
-        z = (int)(r / ny);
-    } else {
-        const int nseg = (nx + BLK - 1) / BLK;
-        const int row = blockIdx.x / nseg, seg = blockIdx.x - row * nseg;
-        x = nx - (nseg - seg) * BLK + tid;
-        y = row;
-        z = 0;
-        active = x >= 0;
-        cell = (int64_t)x + (int64_t)nx * y;
-    }
+    int64_t cell, wi;
+    int64_t oxm, oxp, ozm, ozp, sy, sz;
+    bool bottom, top;
+};
 
-    S *__restrict__ A = (S *)P.pops;
-    const T *__restrict__ u_rd = (const T *)P.u[rd];
-    T *__restrict__ u_wr = (T *)P.u[rd ^ 1];
-    const T *__restrict__ nt_rd = (const T *)P.nt[rd];
-    T *__restrict__ nt_wr = (T *)P.nt[rd ^ 1];
+template <bool PLATE> __device__ __forceinline__ Cell make_cell(const KP &P, int x, int y, int z, bool active)
+{
+    Cell C;
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    C.x = x;
+    C.y = y;
+    C.z = z;
+    C.sy = nx;
+    C.sz = (int64_t)nx * ny;
+    C.cell = (int64_t)x + (int64_t)nx * (y + (int64_t)ny * z);
+    C.oxm = (x == 0) ? (PLATE ? 0 : nx - 1) : -1;
+    C.oxp = (x == nx - 1) ? (PLATE ? 0 : -(int64_t)(nx - 1)) : 1;
+    C.ozm = (z == 0) ? (int64_t)(nz - 1) * C.sz : -C.sz;
+    C.ozp = (z == nz - 1) ? -(int64_t)(nz - 1) * C.sz : C.sz;
+    C.bottom = (y == 0);
+    C.top = (y == ny - 1);
+    C.wi = active ? wall_index(P, x, y, z) : -1;
+    return C;
+}
 
-    const int64_t sy = nx, sz = (int64_t)nx * ny;
-    const int64_t oxm = (x == 0) ? (PLATE ? 0 : nx - 1) : -1;
-    const int64_t oxp = (x == nx - 1) ? (PLATE ? 0 : -(int64_t)(nx - 1)) : 1;
-    const int64_t ozm = (z == 0) ? (int64_t)(nz - 1) * sz : -sz;
-    const int64_t ozp = (z == nz - 1) ? -(int64_t)(nz - 1) * sz : sz;
-    // offset from this cell to the cell x + c (periodic wrap in x for the channel and in z)
-    auto off = [&](int ccx, int ccy, int ccz) -> int64_t {
-        return (ccx > 0 ? oxp : (ccx < 0 ? oxm : 0)) + (int64_t)ccy * sy + (ccz > 0 ? ozp : (ccz < 0 ? ozm : 0));
-    };
+// offset from the cell to the cell x + c
+__device__ __forceinline__ int64_t off(const Cell &C, int ccx, int ccy, int ccz)
+{
+    return (ccx > 0 ? C.oxp : (ccx < 0 ? C.oxm : 0)) + (int64_t)ccy * C.sy + (ccz > 0 ? C.ozp : (ccz < 0 ? C.ozm : 0));
+}
 
-    const bool bottom = (y == 0), top = (y == ny - 1);
-    const int64_t wi = active ? wall_index(P, x, y, z) : -1;
+// ---------------------------------------------------------------------------
+// gather: the incoming populations of one cell (deviations f - w rho0) with
+// the wall links (eq. 31) and symmetry planes resolved; the open-boundary
+// unknowns of the plate are left at 0 for plate_edges.
+// ---------------------------------------------------------------------------
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD>
+__device__ __forceinline__ void gather(const KP &P, const Cell &C, T *f)
+{
+    using SS = Stor<S>;
+    const int64_t N = P.ncell;
+    const int nx = P.nx;
+    const int x = C.x;
+    const bool bottom = C.bottom, top = C.top;
+    const int64_t cell = C.cell, wi = C.wi;
+    const S *__restrict__ A = (const S *)P.pops;
     T rho_w = 0, uwv[3] = {0, 0, 0};
     if (!HRFD && wi >= 0) {
         rho_w = (T)P.wrho[wi];
@@ -116,9 +121,10 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         uwv[1] = (T)P.uw[P.nwall + wi];
         uwv[2] = (T)P.uw[2 * P.nwall + wi];
     }
-
+    const bool active = true;
     // ---- gather the incoming populations (deviations f - w rho0) ----------
-    T f[Q];
+    const bool shifted = P.shift_u != 0.0;
+    const T r0 = (T)P.rho0, Us = (T)P.shift_u;
     sfor<Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ccx = cx<Q>(i), ccy = cy<Q>(i), ccz = cz<Q>(i);
@@ -128,14 +134,18 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         const bool wall = ycross && (top ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, -ccx));
         T v = 0;
         if (active && !xopen) {
+            // the slot holds population i (interior), opp(i) (wall) or mir(i) (symmetry)
             if (!ODD)
-                v = SS::ld(A[i * N + cell]);
+                v = SS::ld(ld_pop(&A[i * N + cell]));
             else if (!ycross)
-                v = SS::ld(A[io * N + cell + off(-ccx, -ccy, -ccz)]);
+                v = SS::ld(ld_pop(&A[io * N + cell + off(C, -ccx, -ccy, -ccz)]));
             else if (wall)
-                v = SS::ld(A[i * N + cell]);
+                v = SS::ld(ld_pop(&A[i * N + cell]));
             else
-                v = SS::ld(A[im * N + cell + off(-ccx, 0, -ccz)]);
+                v = SS::ld(ld_pop(&A[im * N + cell + off(C, -ccx, 0, -ccz)]));
+            if (shifted)
+                v += !ycross ? shift_off<Q, T>(i, r0, Us)
+                             : (wall ? shift_off<Q, T>(opp<Q>(i), r0, Us) : shift_off<Q, T>(mir<Q>(i), r0, Us));
             // eq. 31: f_i = f*_opp(i) + 2 w_i rho_w (c_i . u_w) / cs2
             if (!HRFD && wall && wi >= 0)
                 v += (T)(6.0 * wgt<Q>(i)) * rho_w * ((T)ccx * uwv[0] + (T)ccy * uwv[1] + (T)ccz * uwv[2]);
@@ -143,32 +153,43 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         f[i] = v;
     });
 
-    // ---- plate edges: outlet copy through LDS, Zou-He inlet ---------------
-    if (PLATE) {
-        __shared__ T xch[3][BLK];
-        if (active && x == nx - 2) {
-            xch[0][tid] = f[2];
-            xch[1][tid] = f[6];
-            xch[2][tid] = f[8];
-        }
-        __syncthreads();
-        if (active && x == nx - 1) {
-            f[2] = xch[0][tid - 1];
-            f[6] = xch[1][tid - 1];
-            f[8] = xch[2][tid - 1];
-        }
-        if (active && x == 0) {
-            // Zou-He, u = (U, 0): the known weights sum to 1 in deviation form
-            const T U = (T)P.u_inlet, r0 = (T)P.rho0;
-            T s = f[0] + f[3] + f[4] + (T)2 * (f[2] + f[6] + f[8]);
-            T rho = (r0 + s) / ((T)1 - U);
-            f[1] = f[2] + (T)(2.0 / 3.0) * rho * U;
-            f[5] = f[6] - (T)0.5 * (f[3] - f[4]) + (T)(1.0 / 6.0) * rho * U;
-            f[7] = f[8] + (T)0.5 * (f[3] - f[4]) + (T)(1.0 / 6.0) * rho * U;
-        }
-    }
-    if (!active) return;
+}
 
+// Zou-He inlet (D2Q9, west face, u = (U, 0)): the known weights sum to 1 in
+// deviation form.
+template <typename T> __device__ __forceinline__ void zou_he(const KP &P, T *f)
+{
+    const T U = (T)P.u_inlet, r0 = (T)P.rho0;
+    T s = f[0] + f[3] + f[4] + (T)2 * (f[2] + f[6] + f[8]);
+    T rho = (r0 + s) / ((T)1 - U);
+    f[1] = f[2] + (T)(2.0 / 3.0) * rho * U;
+    f[5] = f[6] - (T)0.5 * (f[3] - f[4]) + (T)(1.0 / 6.0) * rho * U;
+    f[7] = f[8] + (T)0.5 * (f[3] - f[4]) + (T)(1.0 / 6.0) * rho * U;
+}
+
+// ---------------------------------------------------------------------------
+// finish: HRFD reconstruction (wall cells), moments, collision, AA store,
+// velocity, wall density and the Spalart-Allmaras update of one cell.
+// rd: ping-pong index of u^{n-1} / nu_tilde^n; results go to rd ^ 1.
+// ---------------------------------------------------------------------------
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC>
+__device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f)
+{
+    constexpr int D = Lat<Q>::D;
+    using SS = Stor<S>;
+    const int nx = P.nx, ny = P.ny;
+    const int64_t N = P.ncell;
+    const int x = C.x, y = C.y, z = C.z;
+    const bool bottom = C.bottom, top = C.top;
+    const int64_t cell = C.cell, wi = C.wi, sy = C.sy;
+    const int64_t oxm = C.oxm, oxp = C.oxp, ozm = C.ozm, ozp = C.ozp;
+    S *__restrict__ A = (S *)P.pops;
+    const T *__restrict__ u_rd = (const T *)P.u[rd];
+    T *__restrict__ u_wr = (T *)P.u[rd ^ 1];
+    const T *__restrict__ nt_rd = (const T *)P.nt[rd];
+    T *__restrict__ nt_wr = (T *)P.nt[rd ^ 1];
+    const bool shifted = P.shift_u != 0.0;
+    const T r0 = (T)P.rho0, Us = (T)P.shift_u;
     const T nt0 = P.sa_on ? nt_rd[cell] : (T)0;
 
     // ---- HRFD: regularized reconstruction at the wall cells (D2Q9) --------
@@ -263,22 +284,22 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         constexpr int i = decltype(ic)::value;
         constexpr int ccxi = cx<Q>(i), ccyi = cy<Q>(i), cczi = cz<Q>(i);
         constexpr int io = opp<Q>(i), im = mir<Q>(i);
-        const T fp = f[i];
+        const T fp = shifted ? f[i] - shift_off<Q, T>(i, r0, Us) : f[i];
         if (!ODD) {
-            A[io * N + cell] = SS::st(fp);
+            st_pop(&A[io * N + cell], SS::st(fp));
         } else {
             const bool xopen = PLATE && ((ccxi > 0 && x == nx - 1) || (ccxi < 0 && x == 0));
             const bool ycross = (ccyi < 0 && bottom) || (ccyi > 0 && top);
             if (xopen) {
-                A[io * N + cell] = SS::st(fp);
+                st_pop(&A[io * N + cell], SS::st(fp));
             } else if (!ycross) {
-                A[i * N + cell + off(ccxi, ccyi, cczi)] = SS::st(fp);
+                st_pop(&A[i * N + cell + off(C, ccxi, ccyi, cczi)], SS::st(fp));
             } else {
                 const bool wall = top ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, ccxi);
                 if (wall)
-                    A[io * N + cell] = SS::st(fp);
+                    st_pop(&A[io * N + cell], SS::st(fp));
                 else
-                    A[im * N + cell + off(ccxi, 0, cczi)] = SS::st(fp);
+                    st_pop(&A[im * N + cell + off(C, ccxi, 0, cczi)], SS::st(fp));
             }
         }
     });
@@ -325,13 +346,72 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
 }
 
 // ---------------------------------------------------------------------------
+// k_step: one fused LBM-RANS step, one thread per cell.
+// ---------------------------------------------------------------------------
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC>
+__global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
+{
+    const int nx = P.nx, ny = P.ny;
+    const int64_t N = P.ncell;
+    const int tid = threadIdx.x;
+    int x, y, z;
+    bool active;
+    if (!PLATE && P.rowmap) {
+        // XCD k (hardware block b -> XCD b % 8) owns the rows y in
+        // [k ny/8, (k+1) ny/8) for every z, walked z-major: the z+-1 and y+-1
+        // neighbours of the SA stencil are then a few rows apart in one L2.
+        const uint32_t b = blockIdx.x, xcd = b & 7u, l = b >> 3;
+        const uint32_t nseg = (uint32_t)((nx + BLK - 1) / BLK), rows = (uint32_t)ny >> 3;
+        const uint32_t seg = l % nseg, r = l / nseg;
+        y = (int)(xcd * rows + r % rows);
+        z = (int)(r / rows);
+        x = (int)(seg * BLK) + tid;
+        active = x < nx;
+    } else if (!PLATE) {
+        const int64_t cell = xcd_block(blockIdx.x, gridDim.x) * BLK + tid;
+        active = cell < N;
+        const int64_t r = cell / nx;
+        x = (int)(cell - r * nx);
+        y = (int)(r % ny);
+        z = (int)(r / ny);
+    } else {
+        // rows aligned to the right end so that columns nx-2 and nx-1 share a block
+        const int nseg = (nx + BLK - 1) / BLK;
+        const int row = blockIdx.x / nseg, seg = blockIdx.x - row * nseg;
+        x = nx - (nseg - seg) * BLK + tid;
+        y = row;
+        z = 0;
+        active = x >= 0;
+    }
+    const Cell C = make_cell<PLATE>(P, x, y, z, active);
+    T f[Q];
+    if (active) gather<Q, S, T, ODD, PLATE, HRFD>(P, C, f);
+    if (PLATE) {
+        // outlet: unknown populations copied from column nx-2 (through LDS)
+        __shared__ T xch[3][BLK];
+        if (active && x == nx - 2) {
+            xch[0][tid] = f[2];
+            xch[1][tid] = f[6];
+            xch[2][tid] = f[8];
+        }
+        __syncthreads();
+        if (active && x == nx - 1) {
+            f[2] = xch[0][tid - 1];
+            f[6] = xch[1][tid - 1];
+            f[8] = xch[2][tid - 1];
+        }
+        if (active && x == 0) zou_he(P, f);
+    }
+    if (!active) return;
+    finish<Q, S, T, ODD, PLATE, HRFD, CMC>(P, C, rd, f);
+}
+
+// ---------------------------------------------------------------------------
 // k_wall: wall function at every wall cell from u^n (buffer wr); writes the
 // Dirichlet nu_tilde_B into nu_tilde buffer wr.
 // ---------------------------------------------------------------------------
-template <int D, typename T> __global__ void __launch_bounds__(BLK) k_wall(KP P, int wr)
+template <int D, typename T> __device__ __forceinline__ void wall_cell(const KP &P, int64_t w, int wr)
 {
-    const int64_t w = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    if (w >= P.nwall) return;
     const int nx = P.nx, ny = P.ny;
     const int64_t N = P.ncell, sy = nx;
     int x, z, side;
@@ -385,12 +465,30 @@ template <int D, typename T> __global__ void __launch_bounds__(BLK) k_wall(KP P,
     if (P.sa_on) ((T *)P.nt[wr])[B] = (T)(P.nu * P.kappa * yBp);
 }
 
+template <int D, typename T> __global__ void __launch_bounds__(BLK) k_wall(KP P, int wr)
+{
+    const int64_t w = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (w < P.nwall) wall_cell<D, T>(P, w, wr);
+}
+
 // ---------------------------------------------------------------------------
 // Canonical post-collision population f*_i(x) (deviation) of the last step.
 // odd_state: the last step was odd (pushed layout).
 // ---------------------------------------------------------------------------
 template <int Q, int i, typename S, typename T>
+__device__ __forceinline__ T canon_raw(const KP &P, const S *A, int x, int y, int z, int64_t cell, bool odd_state);
+
+// population i of the last step as a deviation f_i - w_i rho0
+template <int Q, int i, typename S, typename T>
 __device__ __forceinline__ T canon_f(const KP &P, const S *A, int x, int y, int z, int64_t cell, bool odd_state)
+{
+    T v = canon_raw<Q, i, S, T>(P, A, x, y, z, cell, odd_state);
+    if (P.shift_u != 0.0) v += shift_off<Q, T>(i, (T)P.rho0, (T)P.shift_u);
+    return v;
+}
+
+template <int Q, int i, typename S, typename T>
+__device__ __forceinline__ T canon_raw(const KP &P, const S *A, int x, int y, int z, int64_t cell, bool odd_state)
 {
     using SS = Stor<S>;
     const int64_t N = P.ncell;
@@ -477,7 +575,8 @@ __global__ void __launch_bounds__(BLK) k_init(KP P, const double *u0, double ux0
         constexpr int i = decltype(ic)::value;
         const double cu = cx<Q>(i) * u[0] + cy<Q>(i) * u[1] + cz<Q>(i) * u[2];
         const double fd = wgt<Q>(i) * P.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        A[opp<Q>(i) * N + cell] = SS::st((T)fd);
+        const double sh = P.shift_u != 0.0 ? (double)shift_off<Q, double>(i, P.rho0, P.shift_u) : 0.0;
+        A[opp<Q>(i) * N + cell] = SS::st((T)(fd - sh));
     });
     T *u_0 = (T *)P.u[0], *us = (T *)P.usnap;
     for (int a = 0; a < D; ++a) {
@@ -522,9 +621,9 @@ __device__ __forceinline__ void block_sum(double (*sh)[BLK], double *v, int nv)
 template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) k_reduce(KP P, bool odd_state, int cur)
 {
     constexpr int D = Lat<Q>::D;
-    __shared__ double sh[7][BLK];
+    __shared__ double sh[8][BLK];
     const int64_t N = P.ncell;
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const S *A = (const S *)P.pops;
     const T *uc = (const T *)P.u[cur];
     T *us = (T *)P.usnap;
@@ -550,9 +649,12 @@ template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) 
         acc[5] += uu;
         acc[6] += bad ? 1.0 : 0.0;
     }
-    block_sum(sh, acc, 7);
+    // slot 7: this block's share of the wall cells' u_tau
+    for (int64_t w = (int64_t)blockIdx.x * BLK + threadIdx.x; w < P.nwall; w += (int64_t)gridDim.x * BLK)
+        acc[7] += P.utau[w];
+    block_sum(sh, acc, 8);
     if (threadIdx.x == 0)
-        for (int k = 0; k < 7; ++k) P.partials[blockIdx.x * NRED + k] = sh[k][0];
+        for (int k = 0; k < 8; ++k) P.partials[blockIdx.x * NRED + k] = sh[k][0];
 }
 
 __global__ void __launch_bounds__(BLK) k_reduce_final(KP P, int nblocks, int slot)
@@ -560,11 +662,139 @@ __global__ void __launch_bounds__(BLK) k_reduce_final(KP P, int nblocks, int slo
     __shared__ double sh[8][BLK];
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblocks; b += BLK)
-        for (int k = 0; k < 7; ++k) acc[k] += P.partials[b * NRED + k];
-    for (int64_t w = threadIdx.x; w < P.nwall; w += BLK) acc[7] += P.utau[w];
+        for (int k = 0; k < 8; ++k) acc[k] += P.partials[b * NRED + k];
     block_sum(sh, acc, 8);
     if (threadIdx.x == 0)
         for (int k = 0; k < 8; ++k) P.result[slot * NRED + k] = sh[k][0];
+}
+
+// ---------------------------------------------------------------------------
+// Serving: persistent kernel over many small D2Q9 lattices, one workgroup per
+// lattice.  Each workgroup loops over time steps with barriers between the
+// phases of a step (fused cell update, wall function, periodic residual) and
+// stops its lattice on convergence, divergence or the step cap.  Every cell
+// update is the same gather/finish code as k_step.
+// ---------------------------------------------------------------------------
+constexpr int SBLK = 256;
+constexpr int SERVE_MAX_NY = 256;  // plate rows held in the outlet exchange buffer
+
+enum { SLOT_IDLE = 0, SLOT_RUNNING = 1, SLOT_CONVERGED = 2, SLOT_CAPPED = 3, SLOT_DIVERGED = 4 };
+
+struct SlotDesc {
+    KP kp;
+    int64_t step, max_steps, snap_step;
+    double tol, residual, mean_utau;
+    int status, reduce_every, variant, pad_;
+};
+
+template <typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC>
+__device__ __forceinline__ void serve_cells(const KP &P, int rd, T (*xch)[SERVE_MAX_NY])
+{
+    const int nx = P.nx;
+    const int64_t N = P.ncell;
+    if (PLATE) {
+        // outlet: the incoming populations of column nx-2 before anyone writes
+        for (int y = threadIdx.x; y < P.ny; y += SBLK) {
+            const Cell Cn = make_cell<true>(P, nx - 2, y, 0, true);
+            T g[9];
+            gather<9, S, T, ODD, true, HRFD>(P, Cn, g);
+            xch[0][y] = g[2];
+            xch[1][y] = g[6];
+            xch[2][y] = g[8];
+        }
+        __syncthreads();
+    }
+    for (int64_t cell = threadIdx.x; cell < N; cell += SBLK) {
+        const int y = (int)(cell / nx), x = (int)(cell - (int64_t)y * nx);
+        const Cell C = make_cell<PLATE>(P, x, y, 0, true);
+        T f[9];
+        gather<9, S, T, ODD, PLATE, HRFD>(P, C, f);
+        if (PLATE) {
+            if (x == nx - 1) {
+                f[2] = xch[0][y];
+                f[6] = xch[1][y];
+                f[8] = xch[2][y];
+            }
+            if (x == 0) zou_he(P, f);
+        }
+        finish<9, S, T, ODD, PLATE, HRFD, CMC>(P, C, rd, f);
+    }
+}
+
+template <typename S, typename T, bool PLATE, bool HRFD, bool CMC>
+__device__ void serve_loop(SlotDesc &SD, int chunk)
+{
+    const KP &P = SD.kp;
+    __shared__ T xch[3][SERVE_MAX_NY];
+    __shared__ double red[8][BLK];
+    __shared__ int stop;
+    int64_t step = SD.step;
+    const int64_t N = P.ncell;
+    if (threadIdx.x == 0) stop = 0;
+    __syncthreads();
+    for (int s = 0; s < chunk; ++s) {
+        const int rd = (int)(step & 1);
+        if ((step + 1) & 1)
+            serve_cells<S, T, true, PLATE, HRFD, CMC>(P, rd, xch);
+        else
+            serve_cells<S, T, false, PLATE, HRFD, CMC>(P, rd, xch);
+        __syncthreads();
+        for (int64_t w = threadIdx.x; w < P.nwall; w += SBLK) wall_cell<2, T>(P, w, rd ^ 1);
+        __syncthreads();
+        ++step;
+        const bool red_now = SD.reduce_every > 0 && step % SD.reduce_every == 0;
+        if (red_now || step >= SD.max_steps) {
+            // residual ||u - u_snap|| / (K ||u||), mean u_tau, NaN check (FP64, fixed order)
+            const T *uc = (const T *)P.u[step & 1];
+            T *us = (T *)P.usnap;
+            double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int64_t cell = threadIdx.x; cell < N; cell += SBLK) {
+                for (int a = 0; a < 2; ++a) {
+                    const double ua = (double)uc[a * N + cell], d = ua - (double)us[a * N + cell];
+                    us[a * N + cell] = uc[a * N + cell];
+                    acc[0] += d * d;
+                    acc[1] += ua * ua;
+                    acc[2] += isfinite(ua) ? 0.0 : 1.0;
+                }
+            }
+            for (int64_t w = threadIdx.x; w < P.nwall; w += SBLK) acc[3] += P.utau[w];
+            block_sum(red, acc, 4);
+            if (threadIdx.x == 0) {
+                const double K = (double)(step - SD.snap_step);
+                const double r = red[1][0] > 0.0 ? sqrt(red[0][0]) / (K * sqrt(red[1][0])) : 0.0;
+                SD.residual = r;
+                SD.mean_utau = P.nwall > 0 ? red[3][0] / (double)P.nwall : 0.0;
+                SD.snap_step = step;
+                if (red[2][0] > 0.0 || !isfinite(r)) {
+                    SD.status = SLOT_DIVERGED;
+                    stop = 1;
+                } else if (red_now && r < SD.tol) {
+                    SD.status = SLOT_CONVERGED;
+                    stop = 1;
+                } else if (step >= SD.max_steps) {
+                    SD.status = SLOT_CAPPED;
+                    stop = 1;
+                }
+            }
+            __syncthreads();
+            if (stop) break;
+        }
+    }
+    if (threadIdx.x == 0) SD.step = step;
+}
+
+template <typename S, typename T, bool CMC> __global__ void __launch_bounds__(SBLK) k_serve(SlotDesc *slots, int variant, int chunk)
+{
+    SlotDesc &SD = slots[blockIdx.x];
+    if (SD.status != SLOT_RUNNING || SD.variant != variant) return;
+    const bool plate = SD.kp.flow == FLOW_PLATE, hrfd = SD.kp.scheme == WALL_HRFD;
+    if (plate) {
+        if (hrfd) serve_loop<S, T, true, true, CMC>(SD, chunk);
+        else serve_loop<S, T, true, false, CMC>(SD, chunk);
+    } else {
+        if (hrfd) serve_loop<S, T, false, true, CMC>(SD, chunk);
+        else serve_loop<S, T, false, false, CMC>(SD, chunk);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -675,8 +905,8 @@ template <int Q, typename S, typename T> struct Impl {
         const bool plate = h->p.flow == LBM_FLOW_PLATE;
         const bool hrfd = h->p.scheme == LBM_WALL_HRFD;
         dim3 grid;
-        if (plate)
-            grid = dim3((unsigned)(h->ny * ((h->nx + BLK - 1) / BLK)));
+        if (plate || P.rowmap)
+            grid = dim3((unsigned)((int64_t)h->ny * h->nz * ((h->nx + BLK - 1) / BLK)));
         else
             grid = dim3((unsigned)((P.ncell + BLK - 1) / BLK));
         const bool cm = h->p.collision == LBM_COLL_CM;
@@ -817,6 +1047,9 @@ void fill_kp(lbm *h)
     k.cw3 = p.cw3;
     k.cv1 = p.cv1;
     k.rlim = p.rlim;
+    k.shift_u = p.store_shift_u;
+    // row-slab XCD mapping for wide channels (see k_step); flat mapping otherwise
+    k.rowmap = (LBM_ROWMAP && p.flow == LBM_FLOW_CHANNEL && h->nx >= BLK / 2 && h->ny % 8 == 0) ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
         k.wall_u_bottom[a] = p.wall_u_bottom[a];
         k.wall_u_top[a] = p.wall_u_top[a];
@@ -1228,5 +1461,313 @@ int lbm_destroy(lbm_t *h)
 }
 
 const char *lbm_last_error(void) { return g_err; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving pool: one caller-owned device buffer, a slot table, first-fit
+// allocation by footprint.  Small D2Q9 lattices run in the persistent
+// k_serve launch (stream A); larger ones run the regular kernels on stream B,
+// so the two overlap on the device.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t SERVE_SMALL_CELLS = 65536;
+
+struct PoolSlot {
+    bool used = false, small = false;
+    lbm *h = nullptr;
+    int64_t off = 0, bytes = 0;
+    int status = SLOT_IDLE;
+    double tol = 0.0, residual = 0.0, mean_utau = 0.0;
+    int64_t max_steps = 0;
+};
+
+int variant_of(const lbm_params_t &p) { return p.precision * 2 + (p.collision == LBM_COLL_CM ? 1 : 0); }
+
+}  // namespace
+
+struct lbm_pool {
+    char *base;
+    int64_t bytes, desc_bytes;
+    int max_slots;
+    hipStream_t sA, sB;
+    SlotDesc *dslots;
+    std::vector<SlotDesc> hslots;
+    std::vector<PoolSlot> slots;
+    std::map<int64_t, int64_t> freel;  // offset -> size
+};
+
+namespace {
+
+int64_t pool_alloc(lbm_pool *pl, int64_t bytes)
+{
+    bytes = align256(bytes);
+    for (auto it = pl->freel.begin(); it != pl->freel.end(); ++it) {
+        if (it->second >= bytes) {
+            const int64_t off = it->first, rest = it->second - bytes;
+            pl->freel.erase(it);
+            if (rest > 0) pl->freel[off + bytes] = rest;
+            return off;
+        }
+    }
+    return -1;
+}
+
+void pool_free(lbm_pool *pl, int64_t off, int64_t bytes)
+{
+    bytes = align256(bytes);
+    auto it = pl->freel.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != pl->freel.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        pl->freel.erase(nx);
+    }
+    if (it != pl->freel.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            pl->freel.erase(it);
+        }
+    }
+}
+
+template <typename S, typename T, bool CMC> int launch_serve(lbm_pool *pl, int variant, int chunk)
+{
+    hipLaunchKernelGGL((k_serve<S, T, CMC>), dim3(pl->max_slots), dim3(SBLK), 0, pl->sA, pl->dslots, variant, chunk);
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+int serve_variant(lbm_pool *pl, int variant, int chunk)
+{
+    const int prec = variant / 2;
+    const bool cm = variant & 1;
+    switch (prec) {
+    case LBM_F64: return cm ? launch_serve<double, double, true>(pl, variant, chunk) : launch_serve<double, double, false>(pl, variant, chunk);
+    case LBM_F32: return cm ? launch_serve<float, float, true>(pl, variant, chunk) : launch_serve<float, float, false>(pl, variant, chunk);
+    case LBM_F16: return cm ? launch_serve<_Float16, float, true>(pl, variant, chunk) : launch_serve<_Float16, float, false>(pl, variant, chunk);
+    default: return cm ? launch_serve<bf16s, float, true>(pl, variant, chunk) : launch_serve<bf16s, float, false>(pl, variant, chunk);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_pool_create(void *dev_buf, int64_t bytes, int max_slots, void *stream, lbm_pool_t **out)
+{
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > 65536) return fail(LBM_EINVAL, "max_slots must be in [1, 65536]");
+    if (!dev_buf || ((uintptr_t)dev_buf & 255u)) return fail(LBM_EINVAL, "pool buffer must be non-NULL and 256-byte aligned");
+    const int64_t desc = align256((int64_t)max_slots * (int64_t)sizeof(SlotDesc));
+    if (bytes < desc + 4096) return fail(LBM_EINVAL, "pool buffer too small");
+    lbm_pool *pl = new (std::nothrow) lbm_pool();
+    if (!pl) return fail(LBM_ENOMEM, "host allocation failed");
+    pl->base = (char *)dev_buf;
+    pl->bytes = bytes;
+    pl->desc_bytes = desc;
+    pl->max_slots = max_slots;
+    pl->sA = (hipStream_t)stream;
+    hipError_t e = hipStreamCreateWithFlags(&pl->sB, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete pl;
+        return fail(LBM_EHIP, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    pl->dslots = (SlotDesc *)pl->base;
+    pl->hslots.assign(max_slots, SlotDesc{});
+    for (auto &d : pl->hslots) d.status = SLOT_IDLE;
+    pl->slots.assign(max_slots, PoolSlot{});
+    pl->freel[desc] = bytes - desc;
+    e = hipMemcpyAsync(pl->dslots, pl->hslots.data(), sizeof(SlotDesc) * max_slots, hipMemcpyHostToDevice, pl->sA);
+    if (e == hipSuccess) e = hipStreamSynchronize(pl->sA);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(pl->sB);
+        delete pl;
+        return fail(LBM_EHIP, "pool descriptor upload: %s", hipGetErrorString(e));
+    }
+    *out = pl;
+    return LBM_OK;
+}
+
+int64_t lbm_pool_free_bytes(const lbm_pool_t *pl)
+{
+    if (!pl) return fail(LBM_ESTATE, "NULL pool");
+    int64_t best = 0;
+    for (auto &kv : pl->freel) best = kv.second > best ? kv.second : best;
+    return best;
+}
+
+int lbm_pool_admit(lbm_pool_t *pl, lbm_lattice_t lattice, int nx, int ny, int nz, const lbm_params_t *p,
+                   const double *u0_host, double tol, int64_t max_steps, int *slot)
+{
+    if (!pl) return fail(LBM_ESTATE, "NULL pool");
+    if (!slot) return fail(LBM_EINVAL, "slot is NULL");
+    *slot = -1;
+    int64_t need = lbm_footprint(lattice, nx, ny, nz, p);
+    if (need < 0) return (int)need;
+    if (!(tol >= 0.0) || max_steps < 1) return fail(LBM_EINVAL, "tol must be >= 0 and max_steps >= 1");
+    int idx = -1;
+    for (int i = 0; i < pl->max_slots; ++i)
+        if (!pl->slots[i].used) {
+            idx = i;
+            break;
+        }
+    if (idx < 0) return fail(LBM_ENOMEM, "no free slot");
+    const int64_t off = pool_alloc(pl, need);
+    if (off < 0) return fail(LBM_ENOMEM, "no free block of %lld bytes", (long long)need);
+    const bool small = lattice == LBM_D2Q9 && (int64_t)nx * ny <= SERVE_SMALL_CELLS &&
+                       (p->flow == LBM_FLOW_CHANNEL || ny <= SERVE_MAX_NY);
+    lbm *h = nullptr;
+    int rc = lbm_create(lattice, nx, ny, nz, p, pl->base + off, align256(need), small ? pl->sA : pl->sB, &h);
+    if (!rc && u0_host) rc = lbm_set_velocity(h, u0_host, 0);
+    if (rc) {
+        if (h) lbm_destroy(h);
+        pool_free(pl, off, need);
+        return rc;
+    }
+    PoolSlot &S = pl->slots[idx];
+    S = PoolSlot{};
+    S.used = true;
+    S.small = small;
+    S.h = h;
+    S.off = off;
+    S.bytes = need;
+    S.status = SLOT_RUNNING;
+    S.tol = tol;
+    S.max_steps = max_steps;
+    if (small) {
+        SlotDesc &d = pl->hslots[idx];
+        d = SlotDesc{};
+        d.kp = h->kp;
+        d.step = 0;
+        d.snap_step = 0;
+        d.max_steps = max_steps;
+        d.tol = tol;
+        d.status = SLOT_RUNNING;
+        d.reduce_every = h->p.reduce_every > 0 ? h->p.reduce_every : 100;
+        d.variant = variant_of(h->p);
+        HIPCHK(hipMemcpyAsync(pl->dslots + idx, &d, sizeof d, hipMemcpyHostToDevice, pl->sA));
+        HIPCHK(hipStreamSynchronize(pl->sA));
+    }
+    *slot = idx;
+    return LBM_OK;
+}
+
+int lbm_pool_step(lbm_pool_t *pl, int64_t steps)
+{
+    if (!pl) return fail(LBM_ESTATE, "NULL pool");
+    if (steps < 1 || steps > (1 << 30)) return fail(LBM_EINVAL, "steps must be in [1, 2^30]");
+    bool variants[8] = {false};
+    bool any_small = false;
+    for (int i = 0; i < pl->max_slots; ++i) {
+        const PoolSlot &S = pl->slots[i];
+        if (S.used && S.small && S.status == SLOT_RUNNING) {
+            variants[pl->hslots[i].variant & 7] = true;
+            any_small = true;
+        }
+    }
+    // small lattices: persistent launches on stream A
+    for (int v = 0; v < 8; ++v)
+        if (variants[v]) {
+            int rc = serve_variant(pl, v, (int)steps);
+            if (rc) return rc;
+        }
+    // large lattices: regular kernels on stream B (overlapping with A)
+    for (int i = 0; i < pl->max_slots; ++i) {
+        PoolSlot &S = pl->slots[i];
+        if (!S.used || S.small || S.status != SLOT_RUNNING) continue;
+        int64_t n = steps;
+        if (S.h->step + n > S.max_steps) n = S.max_steps - S.h->step;
+        if (n > 0) {
+            int rc = lbm_step(S.h, n);
+            if (rc) return rc;
+        }
+    }
+    for (int i = 0; i < pl->max_slots; ++i) {
+        PoolSlot &S = pl->slots[i];
+        if (!S.used || S.small || S.status != SLOT_RUNNING) continue;
+        lbm_residual_t r;
+        int rc = lbm_residual(S.h, &r);
+        S.residual = r.l2_du_rel;
+        S.mean_utau = r.mean_u_tau;
+        if (rc == LBM_EDIVERGED)
+            S.status = SLOT_DIVERGED;
+        else if (rc)
+            return rc;
+        else if (r.l2_du_rel < S.tol && r.steps_since_previous > 0)
+            S.status = SLOT_CONVERGED;
+        else if (S.h->step >= S.max_steps)
+            S.status = SLOT_CAPPED;
+    }
+    if (any_small) {
+        HIPCHK(hipMemcpyAsync(pl->hslots.data(), pl->dslots, sizeof(SlotDesc) * pl->max_slots, hipMemcpyDeviceToHost, pl->sA));
+        HIPCHK(hipStreamSynchronize(pl->sA));
+        for (int i = 0; i < pl->max_slots; ++i) {
+            PoolSlot &S = pl->slots[i];
+            if (!S.used || !S.small) continue;
+            const SlotDesc &d = pl->hslots[i];
+            S.status = d.status;
+            S.residual = d.residual;
+            S.mean_utau = d.mean_utau;
+            S.h->step = d.step;
+            S.h->last_reduce_step = -1;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_pool_poll(lbm_pool_t *pl, int slot, lbm_pool_status_t *out)
+{
+    if (!pl) return fail(LBM_ESTATE, "NULL pool");
+    if (slot < 0 || slot >= pl->max_slots || !pl->slots[slot].used) return fail(LBM_EINVAL, "bad slot %d", slot);
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    const PoolSlot &S = pl->slots[slot];
+    out->status = S.status;
+    out->batched = S.small ? 1 : 0;
+    out->steps = S.h->step;
+    out->residual = S.residual;
+    out->mean_u_tau = S.mean_utau;
+    out->footprint = S.bytes;
+    return LBM_OK;
+}
+
+lbm_t *lbm_pool_lattice(lbm_pool_t *pl, int slot)
+{
+    if (!pl || slot < 0 || slot >= pl->max_slots || !pl->slots[slot].used) return nullptr;
+    return pl->slots[slot].h;
+}
+
+int lbm_pool_release(lbm_pool_t *pl, int slot)
+{
+    if (!pl) return fail(LBM_ESTATE, "NULL pool");
+    if (slot < 0 || slot >= pl->max_slots || !pl->slots[slot].used) return fail(LBM_EINVAL, "bad slot %d", slot);
+    PoolSlot &S = pl->slots[slot];
+    HIPCHK(hipStreamSynchronize(pl->sA));
+    HIPCHK(hipStreamSynchronize(pl->sB));
+    if (S.small) {
+        SlotDesc &d = pl->hslots[slot];
+        d.status = SLOT_IDLE;
+        HIPCHK(hipMemcpyAsync(&pl->dslots[slot].status, &d.status, sizeof d.status, hipMemcpyHostToDevice, pl->sA));
+        HIPCHK(hipStreamSynchronize(pl->sA));
+    }
+    lbm_destroy(S.h);
+    pool_free(pl, S.off, S.bytes);
+    S = PoolSlot{};
+    return LBM_OK;
+}
+
+int lbm_pool_destroy(lbm_pool_t *pl)
+{
+    if (!pl) return fail(LBM_ESTATE, "NULL pool");
+    (void)hipStreamSynchronize(pl->sA);
+    (void)hipStreamSynchronize(pl->sB);
+    for (auto &S : pl->slots)
+        if (S.used && S.h) lbm_destroy(S.h);
+    (void)hipStreamDestroy(pl->sB);
+    delete pl;
+    return LBM_OK;
+}
 
 }  // extern "C"

@@ -96,6 +96,45 @@ template <> struct Stor<bf16s> {
     }
 };
 
+// Storage offset of population i: f_eq_i(rho0, (U, 0, 0)) - w_i rho0.  The
+// stored value of population i is (f_i - w_i rho0) - shift_off<Q>(i, ...).
+template <int Q, typename T> __device__ __forceinline__ T shift_off(int i, T rho0, T U)
+{
+    const T cu = (T)cx<Q>(i) * U;
+    return (T)wgt<Q>(i) * rho0 * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * U * U);
+}
+
+// Population loads/stores.  With LBM_NT_POPS the streamed populations use
+// non-temporal accesses, leaving L2 to the re-read stencil fields.
+#ifndef LBM_NT_POPS
+#define LBM_NT_POPS 1
+#endif
+template <typename S> __device__ __forceinline__ S ld_pop(const S *p)
+{
+#if LBM_NT_POPS
+    if constexpr (std::is_same<S, bf16s>::value) {
+        bf16s r;
+        r.b = __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(p));
+        return r;
+    } else {
+        return __builtin_nontemporal_load(p);
+    }
+#else
+    return *p;
+#endif
+}
+template <typename S> __device__ __forceinline__ void st_pop(S *p, S v)
+{
+#if LBM_NT_POPS
+    if constexpr (std::is_same<S, bf16s>::value)
+        __builtin_nontemporal_store(v.b, reinterpret_cast<uint16_t *>(p));
+    else
+        __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // Kernel parameters (by value).
 // ---------------------------------------------------------------------------
@@ -103,12 +142,14 @@ struct KP {
     int nx, ny, nz, flow;
     int64_t ncell;
     int scheme, law, sa_on, plate_start;
+    int rowmap, pad_;
     int64_t nwall;
     double nu, rho0, fx, fy, fz, u_inlet;
     double kappa, B, beta;
     double reC;          // Reichardt constant C = B - ln(kappa)/kappa
     double cb1, cb2, sigma, cw1, cw2, cw3, cv1, rlim;
     double wall_u_bottom[3], wall_u_top[3];
+    double shift_u;      // storage shift: stored = f - f_eq(rho0, (shift_u, 0, 0))
     void *pops;          // Q * ncell storage
     void *u[2];          // D * ncell compute type, ping-pong
     void *nt[2];         // ncell compute type, ping-pong
@@ -207,8 +248,9 @@ __device__ __forceinline__ void uplus_both(const KP &P, double y, double &u, dou
 
 // Friction velocity from u_t = u_tau u+(y u_tau / nu) (Sec. 3.1): Newton in
 // FP64 from a warm start, safeguarded by a bracket of the unique root (G is
-// increasing).  Quadratic convergence: once a correction is below 1e-12 of
-// u_tau the corrected value is exact to round-off.
+// increasing).  Quadratic convergence: once a correction is below 1e-10 of
+// u_tau the corrected value is exact to round-off (its error is of the order
+// of the square of that correction).
 __device__ __forceinline__ double solve_utau(const KP &P, double ut, double y, double warm)
 {
     if (!(ut > 0.0)) return 0.0;
@@ -228,7 +270,7 @@ __device__ __forceinline__ double solve_utau(const KP &P, double ut, double y, d
         double un = u - g / (up + yp * dup);
         const bool inside = un > lo && un < hi;
         if (!inside) un = hi < 1.0e299 ? 0.5 * (lo + hi) : 2.0 * u;
-        if (inside && fabs(un - u) <= 1.0e-12 * un) return un;
+        if (inside && fabs(un - u) <= 1.0e-10 * un) return un;
         u = un;
     }
     return u;

@@ -44,7 +44,7 @@ class lbm_params_t(ctypes.Structure):
         ("nut_init_ratio", ctypes.c_double), ("kappa", ctypes.c_double), ("B", ctypes.c_double),
         ("beta", ctypes.c_double), ("cb1", ctypes.c_double), ("cb2", ctypes.c_double),
         ("sigma", ctypes.c_double), ("cw2", ctypes.c_double), ("cw3", ctypes.c_double),
-        ("cv1", ctypes.c_double), ("rlim", ctypes.c_double),
+        ("cv1", ctypes.c_double), ("rlim", ctypes.c_double), ("store_shift_u", ctypes.c_double),
     ]
 
 
@@ -55,6 +55,17 @@ class lbm_residual_t(ctypes.Structure):
         ("l2_du_rel", ctypes.c_double), ("mean_u_tau", ctypes.c_double),
         ("d_u_tau_rel", ctypes.c_double), ("nan_flag", ctypes.c_double),
     ]
+
+
+class lbm_pool_status_t(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("batched", ctypes.c_int32), ("steps", ctypes.c_int64),
+        ("residual", ctypes.c_double), ("mean_u_tau", ctypes.c_double),
+        ("footprint", ctypes.c_int64),
+    ]
+
+
+LBM_SLOT_IDLE, LBM_SLOT_RUNNING, LBM_SLOT_CONVERGED, LBM_SLOT_CAPPED, LBM_SLOT_DIVERGED = range(5)
 
 
 class lbm_timing_t(ctypes.Structure):
@@ -101,6 +112,16 @@ def lib() -> ctypes.CDLL:
         "lbm_load": (ctypes.c_int, [vp, vp, i64]),
         "lbm_destroy": (ctypes.c_int, [vp]),
         "lbm_last_error": (ctypes.c_char_p, []),
+        "lbm_pool_create": (ctypes.c_int, [vp, i64, ctypes.c_int, vp, ctypes.POINTER(vp)]),
+        "lbm_pool_free_bytes": (i64, [vp]),
+        "lbm_pool_admit": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          P, vp, ctypes.c_double, i64,
+                                          ctypes.POINTER(ctypes.c_int)]),
+        "lbm_pool_step": (ctypes.c_int, [vp, i64]),
+        "lbm_pool_poll": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(lbm_pool_status_t)]),
+        "lbm_pool_lattice": (vp, [vp, ctypes.c_int]),
+        "lbm_pool_release": (ctypes.c_int, [vp, ctypes.c_int]),
+        "lbm_pool_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -250,3 +271,84 @@ class Lattice:
     @property
     def steps(self) -> int:
         return int(lib().lbm_steps(self.h))
+
+
+class _View(Lattice):
+    """A lattice handle owned by a pool slot (exports only)."""
+
+    def __init__(self, h, lattice, nx, ny, nz):
+        self.h = ctypes.c_void_p(h)
+        self.lattice, self.nx, self.ny, self.nz = lattice, nx, ny, nz
+        self.D = 2 if lattice == LBM_D2Q9 else 3
+        self.ncell = int(lib().lbm_ncell(self.h))
+        self.nwall = int(lib().lbm_nwall(self.h))
+        self.shape = (nz, ny, nx)
+
+    def close(self):
+        self.h = None  # the pool owns the handle
+
+
+class Pool:
+    """The serving pool of the C ABI (lbm_pool_*) in one torch device buffer."""
+
+    def __init__(self, nbytes: int, max_slots: int = 1024, device="cuda", stream=None):
+        import torch
+
+        self.buffer = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.buffer.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.buffer.device)
+        h = ctypes.c_void_p()
+        _check(lib().lbm_pool_create(ctypes.c_void_p(aligned), nbytes, max_slots,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.dims = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_pool_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def lbm_pool_free_bytes(self) -> int:
+        return int(lib().lbm_pool_free_bytes(self.h))
+
+    def lbm_pool_admit(self, lattice, nx, ny, nz, p, u0=None, tol=1e-8, max_steps=10 ** 6):
+        """Returns the slot index, or None when the pool cannot hold it (LBM_ENOMEM)."""
+        slot = ctypes.c_int(-1)
+        ptr = None
+        if u0 is not None:
+            u0 = np.ascontiguousarray(np.asarray(u0, dtype=np.float64))
+            ptr = _ptr(u0)
+        rc = lib().lbm_pool_admit(self.h, lattice, nx, ny, nz, ctypes.byref(p), ptr, tol,
+                                  int(max_steps), ctypes.byref(slot))
+        if rc == LBM_ENOMEM:
+            return None
+        _check(rc)
+        self.dims[slot.value] = (lattice, nx, ny, nz)
+        return slot.value
+
+    def lbm_pool_step(self, steps: int):
+        _check(lib().lbm_pool_step(self.h, int(steps)))
+
+    def lbm_pool_poll(self, slot: int) -> dict:
+        st = lbm_pool_status_t()
+        _check(lib().lbm_pool_poll(self.h, slot, ctypes.byref(st)))
+        return {"status": st.status, "batched": bool(st.batched), "steps": st.steps,
+                "residual": st.residual, "mean_u_tau": st.mean_u_tau,
+                "footprint": st.footprint}
+
+    def lbm_pool_lattice(self, slot: int) -> Lattice:
+        h = lib().lbm_pool_lattice(self.h, slot)
+        if not h:
+            raise LbmError(LBM_EINVAL, f"bad slot {slot}")
+        return _View(h, *self.dims[slot])
+
+    def lbm_pool_release(self, slot: int):
+        _check(lib().lbm_pool_release(self.h, slot))
+        self.dims.pop(slot, None)

@@ -28,7 +28,8 @@ def L():
 
 def test_exports_every_declared_symbol(L):
     names = _declared()
-    assert "lbm_step" in names and "lbm_create" in names and len(names) >= 20
+    assert "lbm_step" in names and "lbm_create" in names and "lbm_pool_admit" in names
+    assert len(names) >= 28
     lib = L.lib()
     for n in names:
         assert hasattr(lib, n), n

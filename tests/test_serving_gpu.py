@@ -1,0 +1,137 @@
+"""Serving pool on the GPU: the batched paths agree with the oracle and with
+the plain path, and a request's result does not depend on what else is
+resident."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2506_03905_amd import inputs, serving, units
+
+pytestmark = pytest.mark.gpu
+L = pytest.importorskip("paper_2506_03905_amd.lbm")
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _req(i, kind, ny, re_tau, scheme):
+    return {"id": i, "t_arrival": 0.0, "kind": kind, "ny": ny,
+            "nx": 4 if kind == "channel" else 8 * ny, "re_tau": re_tau, "scheme": scheme}
+
+
+def _oracle_for(req, steps):
+    lat, nx, ny, nz, p, _ = serving.request_lattice(req)
+    op = O.params(q=9, nx=nx, ny=ny, nz=1, flow=p.flow, scheme=p.scheme, law=p.law,
+                  sa_on=p.sa_on, plate_start=p.plate_start, nu=p.nu, force=tuple(p.force),
+                  u_inlet=p.u_inlet, beta=p.beta, collision=p.collision)
+    u0 = np.zeros((2, 1, ny, nx))
+    u0[0] = p.u_init[0]
+    o = O.Oracle(op, u0)
+    o.step(steps)
+    return o
+
+
+@pytest.mark.parametrize("req", [_req(0, "channel", 64, 2000.0, "slip_bb"),
+                                 _req(1, "channel", 48, 900.0, "hrfd"),
+                                 _req(2, "plate", 32, 800.0, "slip_bb"),
+                                 _req(3, "plate", 32, 3000.0, "hrfd")])
+def test_batched_fp64_matches_oracle(req):
+    """The persistent small-lattice kernel (FP64 storage) against the oracle."""
+    _gpu()
+    lat, nx, ny, nz, p, _ = serving.request_lattice(req)
+    p.precision = L.LBM_F64
+    pool = L.Pool(64 << 20, max_slots=8)
+    slot = pool.lbm_pool_admit(lat, nx, ny, nz, p, None, 0.0, 300)
+    pool.lbm_pool_step(300)
+    st = pool.lbm_pool_poll(slot)
+    assert st["batched"] and st["steps"] == 300 and st["status"] == L.LBM_SLOT_CAPPED
+    v = pool.lbm_pool_lattice(slot)
+    _, ug, _ = v.lbm_moments()
+    o = _oracle_for(req, 300)
+    assert np.abs(ug - o.u()).max() / np.abs(o.u()).max() < 1e-10
+    ut = v.lbm_wall()["utau"]
+    assert np.abs(ut - o.wall()["utau"]).max() / o.wall()["utau"].max() < 1e-10
+    pool.close()
+
+
+def test_alone_equals_mixed_bitwise():
+    """Each request's fields after the same number of steps are bitwise equal
+    whether it runs alone or together with others (small and large tiers)."""
+    _gpu()
+    reqs = [_req(0, "channel", 64, 2000.0, "slip_bb"), _req(1, "plate", 40, 1200.0, "hrfd"),
+            _req(2, "plate", 320, 5000.0, "slip_bb"), _req(3, "channel", 128, 9000.0, "hrfd")]
+    steps = 400
+
+    def run(subset):
+        pool = L.Pool(2 << 30, max_slots=16)
+        slots = {}
+        for r in subset:
+            lat, nx, ny, nz, p, _ = serving.request_lattice(r)
+            slots[r["id"]] = pool.lbm_pool_admit(lat, nx, ny, nz, p, None, 0.0, steps)
+        pool.lbm_pool_step(150)
+        pool.lbm_pool_step(250)
+        out = {}
+        for i, s in slots.items():
+            st = pool.lbm_pool_poll(s)
+            assert st["steps"] == steps
+            out[i] = (pool.lbm_pool_lattice(s).lbm_moments()[1], st["batched"])
+        pool.close()
+        return out
+
+    mixed = run(reqs)
+    assert mixed[0][1] and mixed[1][1] and not mixed[2][1]
+    for r in reqs:
+        alone = run([r])
+        assert np.array_equal(alone[r["id"]][0], mixed[r["id"]][0]), r
+
+
+def test_batched_matches_plain_path():
+    """Persistent batched kernel vs the per-lattice kernels, FP32."""
+    _gpu()
+    req = _req(0, "channel", 96, 4000.0, "slip_bb")
+    lat, nx, ny, nz, p, _ = serving.request_lattice(req)
+    pool = L.Pool(64 << 20, max_slots=4)
+    slot = pool.lbm_pool_admit(lat, nx, ny, nz, p, None, 0.0, 1000)
+    pool.lbm_pool_step(1000)
+    ub = pool.lbm_pool_lattice(slot).lbm_moments()[1]
+    g = L.Lattice(lat, nx, ny, nz, p)
+    g.lbm_step(1000)
+    up = g.lbm_moments()[1]
+    assert np.abs(ub - up).max() / np.abs(up).max() < 1e-5
+    pool.close()
+
+
+def test_admission_by_footprint_and_release():
+    _gpu()
+    req = _req(0, "channel", 256, 2000.0, "slip_bb")
+    need = serving.footprint(req)
+    # room for the slot descriptors and exactly two lattices
+    pool = L.Pool(2 * need + 16384, max_slots=8)
+    lat, nx, ny, nz, p, _ = serving.request_lattice(req)
+    a = pool.lbm_pool_admit(lat, nx, ny, nz, p, None, 1e-8, 100)
+    b = pool.lbm_pool_admit(lat, nx, ny, nz, p, None, 1e-8, 100)
+    assert a is not None and b is not None
+    assert pool.lbm_pool_admit(lat, nx, ny, nz, p, None, 1e-8, 100) is None  # full
+    pool.lbm_pool_release(a)
+    c = pool.lbm_pool_admit(lat, nx, ny, nz, p, None, 1e-8, 100)
+    assert c is not None
+    pool.lbm_pool_release(b)
+    pool.lbm_pool_release(c)
+    assert pool.lbm_pool_free_bytes() >= 2 * need
+    pool.close()
+
+
+def test_converged_requests_stop():
+    """A loose tolerance stops every request early, at a reduction step."""
+    _gpu()
+    reqs = [_req(i, k, ny, rt, s) for i, (k, ny, rt, s) in
+            enumerate([("channel", 32, 800.0, "slip_bb"), ("channel", 64, 3000.0, "hrfd"),
+                       ("plate", 32, 1000.0, "slip_bb")])]
+    res, summ = serving.run_batched(reqs, 256 << 20, chunk=300, tol=1e-4, max_steps=20000)
+    assert summ["solves"] == 3 and summ["diverged"] == 0
+    for r in res.values():
+        assert r["status"] == L.LBM_SLOT_CONVERGED and r["steps"] % 100 == 0
+        assert r["residual"] < 1e-4
