@@ -12,6 +12,13 @@ steps, the FP64 residual reduction.
 --calibrate-copy times a plain device-to-device copy of known size instead;
 its hardware byte counters give the scale factor for the kernel's counters.
 
+--serving runs the serving workload instead: seeded Poisson arrivals of 2-D
+channel and flat-plate solves (70/30, log-uniform Ny in [32, 1024] and Re_tau
+in [500, 20000], wall scheme drawn per request), each run to an L2 velocity
+residual below 1e-8 or to the step cap, through the batched pool and then one
+at a time through the plain per-lattice path; it prints solves/s and p50/p99
+time-to-result for both.
+
 Prints one JSON line (see the design doc for the fields).
 """
 import argparse
@@ -24,6 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per k_step launch from the FETCH_SIZE / WRITE_SIZE counters of the
+# default workload (void once the kernel sources change)
+TRAFFIC_PROFILE = "k_step_d3q19_512x256x256_f32_traffic.md"
 
 
 def bytes_per_lup(q: int, precision: str, sa: bool = True) -> int:
@@ -60,6 +70,57 @@ def cpu_baseline(nx: int, ny: int, nz: int, lat: dict, steps: int, collision: st
                       f"{steps} steps, FP64, 1 thread, {dt:.1f} s"}
 
 
+def serving_bench(args):
+    import torch
+
+    from paper_2506_03905_amd import inputs, serving
+
+    reqs = inputs.requests(0, args.requests, args.rate)
+    need = sum(serving.footprint(r) for r in reqs)
+    pool_bytes = min(int(need * 1.05) + (64 << 20), 128 << 30)
+
+    def log(msg):
+        print("# " + msg, file=sys.stderr, flush=True)
+
+    print(f"# serving: {len(reqs)} requests, total footprint {need / 1e9:.2f} GB, "
+          f"pool {pool_bytes / 1e9:.2f} GB", file=sys.stderr, flush=True)
+    res_b, sum_b = serving.run_batched(reqs, pool_bytes, chunk=args.chunk, tol=args.tol,
+                                       max_steps=args.max_steps, log=log)
+    torch.cuda.synchronize()
+    nseq = len(reqs) if args.seq_requests < 0 else min(args.seq_requests, len(reqs))
+    seq = reqs[:nseq]
+    res_s, sum_s = serving.run_sequential(seq, tol=args.tol, max_steps=args.max_steps, log=log)
+    # same requests, same result: step counts and end status must agree
+    agree = all(res_b[r["id"]]["status"] == res_s[r["id"]]["status"] and
+                res_b[r["id"]]["steps"] == res_s[r["id"]]["steps"] for r in seq)
+    out = {
+        "metric": "batched solves/s (p99 time-to-result reported) vs sequential plain solves",
+        "value": round(sum_b["solves_per_s"], 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.max_steps,
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serving: {len(reqs)} Poisson requests at {args.rate:g}/s, 70% "
+                               f"2-D channel (4 x Ny) / 30% flat plate (8Ny x Ny), Ny log-uniform "
+                               f"[32, 1024], Re_tau log-uniform [500, 20000], tol {args.tol:g}, "
+                               f"step cap {args.max_steps}, D2Q9 FP32 CM + SA",
+                   "chunk": args.chunk, "parallelism": "single GPU"},
+        "batched": sum_b,
+        "sequential": sum_s,
+        "sequential_requests": nseq,
+        "speedup_solves_per_s": sum_b["solves_per_s"] / sum_s["solves_per_s"]
+                                if nseq and sum_s["solves_per_s"] > 0 else None,
+        "same_steps_and_status": agree,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +136,14 @@ def main():
     ap.add_argument("--amp", type=float, default=0.0)
     ap.add_argument("--sa", default="on", choices=["on", "off"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
+    ap.add_argument("--serving", action="store_true")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--max-steps", type=int, default=20000)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--chunk", type=int, default=500)
+    ap.add_argument("--seq-requests", type=int, default=-1,
+                    help="requests run sequentially (default: all)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; multi-GPU runs are not part of this build "
@@ -98,6 +167,10 @@ def main():
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
         print(json.dumps({"copy_bytes": n, "ms": ms, "GBs_read_plus_write": 2 * n / ms / 1e6}))
+        return
+
+    if args.serving:
+        serving_bench(args)
         return
 
     import paper_2506_03905_amd.lbm as L
@@ -136,8 +209,14 @@ def main():
     bpl = bytes_per_lup(19, args.precision, args.sa == "on")
     k_ms = tm["step_ms"] / max(tm["step_launches"], 1)
     achieved = bpl * ncell / (k_ms * 1e-3) / 1e9
+    traffic = None
+    if (nx, ny, nz, args.precision, args.collision, args.sa, args.amp) == \
+            (512, 256, 256, "f32", "bgk", "on", 0.0):
+        from paper_2506_03905_amd import profile_summary
+        t = profile_summary.read_traffic(os.path.join(ROOT, "profiles", TRAFFIC_PROFILE))
+        traffic = None if t is None else round(t["traffic_bytes"])
     out = {
-        "metric": "MLUPS (D3Q19 stream-collide + SA + slip-velocity bounce-back)",
+        "metric": "MLUPS & % HBM peak (D3Q19 fp32)",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -157,8 +236,9 @@ def main():
                                                              if args.amp else ""),
                    "cells": ncell, "collision": args.collision, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": "k_step", "bytes_per_lup": bpl,
+                     "algorithmic_bytes_per_launch": bpl * ncell,
                      "kernel_ms": round(k_ms, 4),
                      "wall_kernel_ms": round(tm["wall_ms"] / max(tm["wall_launches"], 1), 4)},
         "residual": {"l2_du_rel": res["l2_du_rel"], "mean_u_tau": res["mean_u_tau"],

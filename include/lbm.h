@@ -87,8 +87,17 @@ typedef enum { LBM_FLOW_CHANNEL = 0, LBM_FLOW_PLATE = 1 } lbm_flow_t;
  *   (eq. 19) with rho_B from eq. 23, u_B from the wall function, and the
  *   blended wall-normal gradient of eq. 27-28 (beta = 0.28 calibrated in
  *   Sec. 4.1.2.1; beta = 0 gives the finite-difference regularized BC).
- *   D2Q9 only. */
-typedef enum { LBM_WALL_FIXED_BB = 0, LBM_WALL_SLIP_BB = 1, LBM_WALL_HRFD = 2 } lbm_wall_scheme_t;
+ *   D2Q9 only.
+ * LBM_WALL_CAI_DEGRIGNY: the same reconstruction with the wall-normal
+ *   gradient taken as the third-order one-sided difference of the wall law
+ *   (eq. 29) in place of eq. 27 (Sec. 3.1.2, eq. 30: beta = 1 with the law's
+ *   derivative replaced); the beta argument is ignored.  D2Q9 only. */
+typedef enum {
+    LBM_WALL_FIXED_BB = 0,
+    LBM_WALL_SLIP_BB = 1,
+    LBM_WALL_HRFD = 2,
+    LBM_WALL_CAI_DEGRIGNY = 3
+} lbm_wall_scheme_t;
 
 /* Collision operators (Sec. 2.1).
  * LBM_COLL_BGK: single relaxation time omega = 1/tau_eff with the second-order

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm_oracle.so")
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 
 CHANNEL, PLATE = 0, 1
-BB_FIXED, BB_SLIP, HRFD = 0, 1, 2
+BB_FIXED, BB_SLIP, HRFD, CAI_DEGRIGNY = 0, 1, 2, 3
 REICHARDT, SA_LAW = 0, 1
 BGK, CM = 0, 1
 

@@ -474,7 +474,7 @@ orc *orc_create(const orc_params *p, const double *u0)
     if (p->q == 9 && p->nz != 1) return NULL;
     if (p->nx < 1 || p->ny < 4 || p->nz < 1) return NULL;
     if (p->flow == ORC_PLATE && (p->q != 9 || p->nx < 4)) return NULL;
-    if (p->scheme == ORC_HRFD && p->q != 9) return NULL;
+    if ((p->scheme == ORC_HRFD || p->scheme == ORC_CAI_DEGRIGNY) && p->q != 9) return NULL;
     orc *o = (orc *)calloc(1, sizeof(orc));
     o->p = *p;
     o->D = p->q == 9 ? 2 : 3;
@@ -658,6 +658,11 @@ void orc_hrfd_cell(const orc_params *p, double *f, int side, const double *t, do
     double g_an = utau * utau / p->nu * orc_duplus(p->law, yBp, p->kappa, p->B);
     double g_fd = (-3.0 * ubwf + 4.0 * uF_t - uFF_t) / 2.0;
     double G = p->beta * g_an + (1.0 - p->beta) * g_fd;
+    /* Sec. 3.1.2: the Cai-Degrigny variant takes eq. 27 with beta = 1 and the
+     * third-order difference of the law (eq. 29) in place of its derivative
+     * (eq. 30); the flow at F and FF does not enter */
+    if (p->scheme == ORC_CAI_DEGRIGNY)
+        G = orc_cai_degrigny_grad(p->law, utau, p->nu, yB, 1.0, p->kappa, p->B);
     /* S_ab = (d_a u_b + d_b u_a)/2 with d_{n'} u = t G, d_x u_x = dudx,
      * v_B = 0 along the wall (so d_x u_y = 0) and S_yy = -S_xx */
     double S[9];
@@ -670,7 +675,7 @@ void orc_hrfd_cell(const orc_params *p, double *f, int side, const double *t, do
     orc_regularized(Q, rhoB, uB, S, tau, f);
 }
 
-/* HRFD over every wall cell (Sec. 3.1, eq. 19, 23, 26-28).  Wall state
+/* HRFD (or Cai-Degrigny) over every wall cell (Sec. 3.1, eq. 19, 23, 26-30).  Wall state
  * (u_tau, t) and the velocities at F, FF are those of the previous step;
  * nu_tilde_B is the Dirichlet value set by the previous step. */
 static void hrfd(orc *o)
@@ -791,7 +796,7 @@ void orc_step(orc *o, int64_t n)
 {
     for (int64_t s = 0; s < n; ++s) {
         stream(o);
-        if (o->p.scheme == ORC_HRFD) hrfd(o);
+        if (o->p.scheme == ORC_HRFD || o->p.scheme == ORC_CAI_DEGRIGNY) hrfd(o);
         collide_and_sa(o);
         wall_function(o, o->nt_next);
         double *t = o->nt; o->nt = o->nt_next; o->nt_next = t;

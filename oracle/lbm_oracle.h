@@ -29,6 +29,7 @@ extern "C" {
 #define ORC_BB_FIXED 0 /* halfway bounce-back, prescribed wall velocity (eq. 31) */
 #define ORC_BB_SLIP 1  /* slip-velocity bounce-back (eq. 31 with eq. 35) */
 #define ORC_HRFD 2     /* hybrid regularized reconstruction (eq. 19, 23, 26-28) */
+#define ORC_CAI_DEGRIGNY 3 /* regularized reconstruction with the gradient of eq. 29 (eq. 30) */
 
 /* collision operators */
 #define ORC_BGK 0 /* BGK with Guo forcing */
@@ -42,7 +43,7 @@ typedef struct orc_params {
     int32_t q;           /* 9 (D2Q9) or 19 (D3Q19) */
     int32_t nx, ny, nz;  /* nz = 1 for D2Q9 */
     int32_t flow;        /* ORC_CHANNEL / ORC_PLATE */
-    int32_t scheme;      /* ORC_BB_FIXED / ORC_BB_SLIP / ORC_HRFD */
+    int32_t scheme;      /* ORC_BB_FIXED / ORC_BB_SLIP / ORC_HRFD / ORC_CAI_DEGRIGNY */
     int32_t law;         /* ORC_REICHARDT / ORC_SA_LAW */
     int32_t sa_on;       /* 1: couple Spalart-Allmaras; 0: laminar, nu_t = 0 */
     int32_t plate_start; /* first wall cell of the plate (ORC_PLATE) */

@@ -453,7 +453,14 @@ template <int D, typename T> __device__ __forceinline__ void wall_cell(const KP 
         uw[2] = uBz - s * tz;
     } else {
         P.ubwf[w] = utau * uplus(P, yBp);
-        P.gan[w] = utau * utau / P.nu * duplus(P, yBp);
+        if (P.scheme == WALL_CD) {
+            // eq. 29 with Delta = 1: third-order one-sided difference of the law
+            const double dp = utau / P.nu;
+            P.gan[w] = utau * ((-11.0 / 6.0) * uplus(P, yBp) + 3.0 * uplus(P, yBp + dp) -
+                               1.5 * uplus(P, yBp + 2.0 * dp) + (1.0 / 3.0) * uplus(P, yBp + 3.0 * dp));
+        } else {
+            P.gan[w] = utau * utau / P.nu * duplus(P, yBp);
+        }
     }
     P.utau[w] = utau;
     P.tdir[w] = tx;
@@ -787,7 +794,7 @@ template <typename S, typename T, bool CMC> __global__ void __launch_bounds__(SB
 {
     SlotDesc &SD = slots[blockIdx.x];
     if (SD.status != SLOT_RUNNING || SD.variant != variant) return;
-    const bool plate = SD.kp.flow == FLOW_PLATE, hrfd = SD.kp.scheme == WALL_HRFD;
+    const bool plate = SD.kp.flow == FLOW_PLATE, hrfd = SD.kp.scheme >= WALL_HRFD;
     if (plate) {
         if (hrfd) serve_loop<S, T, true, true, CMC>(SD, chunk);
         else serve_loop<S, T, true, false, CMC>(SD, chunk);
@@ -903,7 +910,7 @@ template <int Q, typename S, typename T> struct Impl {
     {
         const KP &P = h->kp;
         const bool plate = h->p.flow == LBM_FLOW_PLATE;
-        const bool hrfd = h->p.scheme == LBM_WALL_HRFD;
+        const bool hrfd = h->p.scheme >= LBM_WALL_HRFD;
         dim3 grid;
         if (plate || P.rowmap)
             grid = dim3((unsigned)((int64_t)h->ny * h->nz * ((h->nx + BLK - 1) / BLK)));
@@ -1003,8 +1010,8 @@ int check_params(int lattice, int nx, int ny, int nz, const lbm_params_t *p)
     if (p->flow != LBM_FLOW_CHANNEL && p->flow != LBM_FLOW_PLATE) return fail(LBM_EINVAL, "unknown flow %d", p->flow);
     if (p->flow == LBM_FLOW_PLATE && (lattice != LBM_D2Q9 || nx < 4))
         return fail(LBM_EINVAL, "the plate needs D2Q9 and nx >= 4");
-    if (p->scheme < LBM_WALL_FIXED_BB || p->scheme > LBM_WALL_HRFD) return fail(LBM_EINVAL, "unknown wall scheme");
-    if (p->scheme == LBM_WALL_HRFD && lattice != LBM_D2Q9) return fail(LBM_EINVAL, "HRFD is D2Q9 only");
+    if (p->scheme < LBM_WALL_FIXED_BB || p->scheme > LBM_WALL_CAI_DEGRIGNY) return fail(LBM_EINVAL, "unknown wall scheme");
+    if (p->scheme >= LBM_WALL_HRFD && lattice != LBM_D2Q9) return fail(LBM_EINVAL, "HRFD is D2Q9 only");
     if (p->law != LBM_LAW_REICHARDT && p->law != LBM_LAW_SA) return fail(LBM_EINVAL, "unknown wall law");
     if (!(p->nu > 0.0)) return fail(LBM_EINVAL, "nu must be > 0 (tau_eff > 1/2)");
     if (!(p->rho0 > 0.0)) return fail(LBM_EINVAL, "rho0 must be > 0");
@@ -1037,7 +1044,7 @@ void fill_kp(lbm *h)
     k.u_inlet = p.u_inlet;
     k.kappa = p.kappa;
     k.B = p.B;
-    k.beta = p.beta;
+    k.beta = p.scheme == LBM_WALL_CAI_DEGRIGNY ? 1.0 : p.beta;  // eq. 30
     k.reC = p.B - log(p.kappa) / p.kappa;
     k.cb1 = p.cb1;
     k.cb2 = p.cb2;
@@ -1234,12 +1241,12 @@ int lbm_set_velocity(lbm_t *h, const double *u, int on_device)
 int lbm_set_wall_bc(lbm_t *h, lbm_wall_scheme_t scheme, double beta)
 {
     if (!h) return fail(LBM_ESTATE, "NULL handle");
-    if (scheme < LBM_WALL_FIXED_BB || scheme > LBM_WALL_HRFD) return fail(LBM_EINVAL, "unknown wall scheme");
-    if (scheme == LBM_WALL_HRFD && h->Q != 9) return fail(LBM_EINVAL, "HRFD is D2Q9 only");
+    if (scheme < LBM_WALL_FIXED_BB || scheme > LBM_WALL_CAI_DEGRIGNY) return fail(LBM_EINVAL, "unknown wall scheme");
+    if (scheme >= LBM_WALL_HRFD && h->Q != 9) return fail(LBM_EINVAL, "HRFD is D2Q9 only");
     h->p.scheme = scheme;
     h->p.beta = beta;
     h->kp.scheme = scheme;
-    h->kp.beta = beta;
+    h->kp.beta = scheme == LBM_WALL_CAI_DEGRIGNY ? 1.0 : beta;  // eq. 30
     // refresh the wall state for the new scheme from the current velocity
     return LBM_DISPATCH(h, wall, h, (int)(h->step & 1));
 }

@@ -165,7 +165,7 @@ struct KP {
 };
 
 constexpr int FLOW_CHANNEL = 0, FLOW_PLATE = 1;
-constexpr int WALL_FIXED = 0, WALL_SLIP = 1, WALL_HRFD = 2;
+constexpr int WALL_FIXED = 0, WALL_SLIP = 1, WALL_HRFD = 2, WALL_CD = 3;
 constexpr int LAW_REICHARDT = 0, LAW_SA = 1;
 
 // wall index of a boundary cell (or -1)

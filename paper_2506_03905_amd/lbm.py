@@ -18,12 +18,13 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EDIVERGED, LBM_ESTATE = 0, -1, -2,
 LBM_D2Q9, LBM_D3Q19 = 9, 19
 LBM_F64, LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2, 3
 LBM_FLOW_CHANNEL, LBM_FLOW_PLATE = 0, 1
-LBM_WALL_FIXED_BB, LBM_WALL_SLIP_BB, LBM_WALL_HRFD = 0, 1, 2
+LBM_WALL_FIXED_BB, LBM_WALL_SLIP_BB, LBM_WALL_HRFD, LBM_WALL_CAI_DEGRIGNY = 0, 1, 2, 3
 LBM_LAW_REICHARDT, LBM_LAW_SA = 0, 1
 LBM_COLL_BGK, LBM_COLL_CM = 0, 1
 
 PRECISION = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
-SCHEME = {"fixed_bb": LBM_WALL_FIXED_BB, "slip_bb": LBM_WALL_SLIP_BB, "hrfd": LBM_WALL_HRFD}
+SCHEME = {"fixed_bb": LBM_WALL_FIXED_BB, "slip_bb": LBM_WALL_SLIP_BB, "hrfd": LBM_WALL_HRFD,
+          "cai_degrigny": LBM_WALL_CAI_DEGRIGNY}
 
 
 class LbmError(RuntimeError):

@@ -354,6 +354,42 @@ def test_cai_degrigny_ratio_fig5():
     assert abs(num / ana - lim) < 1e-6
 
 
+@pytest.mark.parametrize("law", [O.REICHARDT, O.SA_LAW])
+def test_cai_degrigny_stencil_third_order(law):
+    """eq. 29 is a one-sided third-order difference: at a fixed y_B its error
+    against the law's derivative falls by 2^3 when Delta halves."""
+    nu, utau, yB = 1.0, 1.0, 8.0
+    ana = utau ** 2 / nu * O.duplus(law, yB * utau / nu)
+    errs = [O.cai_degrigny_grad(law, utau, nu, yB, d) - ana for d in (0.1, 0.05, 0.025)]
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 7.0 < e0 / e1 < 9.0, errs
+
+
+@pytest.mark.parametrize("side", [-1, 1])
+def test_cai_degrigny_cell(side):
+    """The Cai-Degrigny scheme (Sec. 3.1.2, eq. 30) is the regularized cell of
+    eq. 26 with the wall-normal gradient of eq. 29 at Delta = 1, y_B = 1/2:
+    the flow at F, FF and beta do not enter, and in the log layer that
+    gradient is 0.76-0.77 of the law's derivative (Fig. 5)."""
+    c, w, _ = O.lattice(9)
+    cc = c[:, :2].astype(float)
+    nu, utau, ntB = 1e-5, 4e-3, 2e-3  # y_B+ = 200
+    f = O.feq(9, 1.01, (0.04, 0.0))
+    tau = 0.5 + 3 * (nu + O.nut(O.params(q=9, nu=nu), ntB))
+    outs = []
+    for beta, uF, uFF in ((0.28, 0.05, 0.06), (0.0, 0.01, 0.0), (1.0, 0.0, 0.3)):
+        p = O.params(q=9, nu=nu, law=O.SA_LAW, beta=beta, sa_on=1, scheme=O.CAI_DEGRIGNY)
+        outs.append(O.hrfd_cell(p, f, side, (1, 0), utau, uF, uFF, 0.0, ntB))
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    out = outs[0]
+    rhoB = out.sum()
+    G = O.cai_degrigny_grad(O.SA_LAW, utau, nu, 0.5, 1.0)
+    Pxy = out @ (cc[:, 0] * cc[:, 1])
+    assert abs(Pxy - (-2 * rhoB * tau / 3 * 0.5 * (-side * G))) < 1e-15
+    ana = utau ** 2 / nu * O.duplus(O.SA_LAW, 0.5 * utau / nu)
+    assert 0.755 < G / ana < 0.775
+
+
 # -------------------------------------------------------------------- P13 -----
 def _loglayer_rhs(y, utau=0.05, nu=1e-9):
     p = O.params(q=9, nu=nu)

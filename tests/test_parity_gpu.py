@@ -79,12 +79,13 @@ def test_d2q9_channel_slip_bb_f64(steps):
     _compare_f64(o, g)
 
 
+@pytest.mark.parametrize("scheme", [O.HRFD, O.CAI_DEGRIGNY])
 @pytest.mark.parametrize("law", [O.REICHARDT, O.SA_LAW])
-def test_d2q9_channel_hrfd_f64(law):
+def test_d2q9_channel_hrfd_f64(law, scheme):
     lat = units.channel(4200.0, 10)
     nx, ny = 6, 20
     u0 = _channel_u0(9, nx, ny, 1, lat["u_bulk"])
-    o, g = _pair(9, nx, ny, 1, scheme=O.HRFD, u0=u0, nu=lat["nu"], law=law,
+    o, g = _pair(9, nx, ny, 1, scheme=scheme, u0=u0, nu=lat["nu"], law=law,
                  force=(lat["force"], 0, 0))
     o.step(40)
     g.lbm_step(40)
@@ -115,7 +116,7 @@ def test_d3q19_channel_slip_bb_f64(steps):
     _compare_f64(o, g)
 
 
-@pytest.mark.parametrize("scheme", [O.BB_SLIP, O.HRFD])
+@pytest.mark.parametrize("scheme", [O.BB_SLIP, O.HRFD, O.CAI_DEGRIGNY])
 @pytest.mark.parametrize("steps", [1, 2, 60])
 def test_d2q9_plate_f64(scheme, steps):
     nx, ny, U = 300, 12, 0.05
