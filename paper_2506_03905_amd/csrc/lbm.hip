@@ -70,10 +70,20 @@ struct Cell {
     int x, y, z;
     int64_t cell, wi;
     int64_t oxm, oxp, ozm, ozp, sy, sz;
+    int64_t pb;  // index of population 0 of this cell in the row-interleaved layout
     bool bottom, top;
 };
 
-template <bool PLATE> __device__ __forceinline__ Cell make_cell(const KP &P, int x, int y, int z, bool active)
+// Population storage is row-interleaved: each row of nx cells (fixed y, z)
+// holds its Q populations as Q consecutive runs of nx values,
+//   index(q, x, row) = (row * Q + q) * nx + x,   row = y + ny z,
+// so one row's populations form one contiguous block of HBM.
+template <int Q> __device__ __forceinline__ int64_t pidx(int nx, int q, int x, int64_t row)
+{
+    return (row * Q + q) * (int64_t)nx + x;
+}
+
+template <int Q, bool PLATE> __device__ __forceinline__ Cell make_cell(const KP &P, int x, int y, int z, bool active)
 {
     Cell C;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
@@ -83,6 +93,7 @@ template <bool PLATE> __device__ __forceinline__ Cell make_cell(const KP &P, int
     C.sy = nx;
     C.sz = (int64_t)nx * ny;
     C.cell = (int64_t)x + (int64_t)nx * (y + (int64_t)ny * z);
+    C.pb = pidx<Q>(nx, 0, x, y + (int64_t)ny * z);
     C.oxm = (x == 0) ? (PLATE ? 0 : nx - 1) : -1;
     C.oxp = (x == nx - 1) ? (PLATE ? 0 : -(int64_t)(nx - 1)) : 1;
     C.ozm = (z == 0) ? (int64_t)(nz - 1) * C.sz : -C.sz;
@@ -99,6 +110,13 @@ __device__ __forceinline__ int64_t off(const Cell &C, int ccx, int ccy, int ccz)
     return (ccx > 0 ? C.oxp : (ccx < 0 ? C.oxm : 0)) + (int64_t)ccy * C.sy + (ccz > 0 ? C.ozp : (ccz < 0 ? C.ozm : 0));
 }
 
+// offset, in the population layout, from slot (q, x) to slot (q, x + c)
+template <int Q> __device__ __forceinline__ int64_t poff(const Cell &C, int ccx, int ccy, int ccz)
+{
+    return (ccx > 0 ? C.oxp : (ccx < 0 ? C.oxm : 0)) +
+           (int64_t)Q * ((int64_t)ccy * C.sy + (ccz > 0 ? C.ozp : (ccz < 0 ? C.ozm : 0)));
+}
+
 // ---------------------------------------------------------------------------
 // gather: the incoming populations of one cell (deviations f - w rho0) with
 // the wall links (eq. 31) and symmetry planes resolved; the open-boundary
@@ -108,11 +126,10 @@ template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD>
 __device__ __forceinline__ void gather(const KP &P, const Cell &C, T *f)
 {
     using SS = Stor<S>;
-    const int64_t N = P.ncell;
     const int nx = P.nx;
     const int x = C.x;
     const bool bottom = C.bottom, top = C.top;
-    const int64_t cell = C.cell, wi = C.wi;
+    const int64_t pb = C.pb, wi = C.wi;
     const S *__restrict__ A = (const S *)P.pops;
     T rho_w = 0, uwv[3] = {0, 0, 0};
     if (!HRFD && wi >= 0) {
@@ -136,13 +153,13 @@ __device__ __forceinline__ void gather(const KP &P, const Cell &C, T *f)
         if (active && !xopen) {
             // the slot holds population i (interior), opp(i) (wall) or mir(i) (symmetry)
             if (!ODD)
-                v = SS::ld(ld_pop(&A[i * N + cell]));
+                v = SS::ld(ld_pop(&A[pb + i * nx]));
             else if (!ycross)
-                v = SS::ld(ld_pop(&A[io * N + cell + off(C, -ccx, -ccy, -ccz)]));
+                v = SS::ld(ld_pop(&A[pb + io * nx + poff<Q>(C, -ccx, -ccy, -ccz)]));
             else if (wall)
-                v = SS::ld(ld_pop(&A[i * N + cell]));
+                v = SS::ld(ld_pop(&A[pb + i * nx]));
             else
-                v = SS::ld(ld_pop(&A[im * N + cell + off(C, -ccx, 0, -ccz)]));
+                v = SS::ld(ld_pop(&A[pb + im * nx + poff<Q>(C, -ccx, 0, -ccz)]));
             if (shifted)
                 v += !ycross ? shift_off<Q, T>(i, r0, Us)
                              : (wall ? shift_off<Q, T>(opp<Q>(i), r0, Us) : shift_off<Q, T>(mir<Q>(i), r0, Us));
@@ -181,7 +198,7 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f)
     const int64_t N = P.ncell;
     const int x = C.x, y = C.y, z = C.z;
     const bool bottom = C.bottom, top = C.top;
-    const int64_t cell = C.cell, wi = C.wi, sy = C.sy;
+    const int64_t cell = C.cell, wi = C.wi, sy = C.sy, pb = C.pb;
     const int64_t oxm = C.oxm, oxp = C.oxp, ozm = C.ozm, ozp = C.ozp;
     S *__restrict__ A = (S *)P.pops;
     const T *__restrict__ u_rd = (const T *)P.u[rd];
@@ -286,20 +303,20 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f)
         constexpr int io = opp<Q>(i), im = mir<Q>(i);
         const T fp = shifted ? f[i] - shift_off<Q, T>(i, r0, Us) : f[i];
         if (!ODD) {
-            st_pop(&A[io * N + cell], SS::st(fp));
+            st_pop(&A[pb + io * nx], SS::st(fp));
         } else {
             const bool xopen = PLATE && ((ccxi > 0 && x == nx - 1) || (ccxi < 0 && x == 0));
             const bool ycross = (ccyi < 0 && bottom) || (ccyi > 0 && top);
             if (xopen) {
-                st_pop(&A[io * N + cell], SS::st(fp));
+                st_pop(&A[pb + io * nx], SS::st(fp));
             } else if (!ycross) {
-                st_pop(&A[i * N + cell + off(C, ccxi, ccyi, cczi)], SS::st(fp));
+                st_pop(&A[pb + i * nx + poff<Q>(C, ccxi, ccyi, cczi)], SS::st(fp));
             } else {
                 const bool wall = top ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, ccxi);
                 if (wall)
-                    st_pop(&A[io * N + cell], SS::st(fp));
+                    st_pop(&A[pb + io * nx], SS::st(fp));
                 else
-                    st_pop(&A[im * N + cell + off(C, ccxi, 0, cczi)], SS::st(fp));
+                    st_pop(&A[pb + im * nx + poff<Q>(C, ccxi, 0, cczi)], SS::st(fp));
             }
         }
     });
@@ -383,7 +400,7 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         z = 0;
         active = x >= 0;
     }
-    const Cell C = make_cell<PLATE>(P, x, y, z, active);
+    const Cell C = make_cell<Q, PLATE>(P, x, y, z, active);
     T f[Q];
     if (active) gather<Q, S, T, ODD, PLATE, HRFD>(P, C, f);
     if (PLATE) {
@@ -498,22 +515,22 @@ template <int Q, int i, typename S, typename T>
 __device__ __forceinline__ T canon_raw(const KP &P, const S *A, int x, int y, int z, int64_t cell, bool odd_state)
 {
     using SS = Stor<S>;
-    const int64_t N = P.ncell;
     constexpr int io = opp<Q>(i), im = mir<Q>(i);
-    if (!odd_state) return SS::ld(A[io * N + cell]);
     const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int64_t row = y + (int64_t)ny * z;
+    if (!odd_state) return SS::ld(A[pidx<Q>(nx, io, x, row)]);
     constexpr int ccx = cx<Q>(i), ccy = cy<Q>(i), ccz = cz<Q>(i);
     const bool plate = P.flow == FLOW_PLATE;
     const bool xopen = plate && ((ccx > 0 && x == nx - 1) || (ccx < 0 && x == 0));
     const bool ycross = (ccy < 0 && y == 0) || (ccy > 0 && y == ny - 1);
-    if (xopen) return SS::ld(A[io * N + cell]);
+    if (xopen) return SS::ld(A[pidx<Q>(nx, io, x, row)]);
     int xd = x + ccx, zd = z + ccz;
     if (!plate) xd = (xd + nx) % nx;
     zd = (zd + nz) % nz;
-    if (!ycross) return SS::ld(A[i * N + xd + (int64_t)nx * (y + ccy + (int64_t)ny * zd)]);
+    if (!ycross) return SS::ld(A[pidx<Q>(nx, i, xd, y + ccy + (int64_t)ny * zd)]);
     const bool wall = (y == ny - 1 && ccy > 0) ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, ccx);
-    if (wall) return SS::ld(A[io * N + cell]);
-    return SS::ld(A[im * N + xd + (int64_t)nx * (y + (int64_t)ny * zd)]);
+    if (wall) return SS::ld(A[pidx<Q>(nx, io, x, row)]);
+    return SS::ld(A[pidx<Q>(nx, im, xd, y + (int64_t)ny * zd)]);
 }
 
 template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) k_export_f(KP P, bool odd_state, double *out)
@@ -578,12 +595,14 @@ __global__ void __launch_bounds__(BLK) k_init(KP P, const double *u0, double ux0
         for (int a = 0; a < D; ++a) u[a] = u0[a * N + cell];
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     S *A = (S *)P.pops;
+    const int64_t row = cell / P.nx;
+    const int x = (int)(cell - row * P.nx);
     sfor<Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const double cu = cx<Q>(i) * u[0] + cy<Q>(i) * u[1] + cz<Q>(i) * u[2];
         const double fd = wgt<Q>(i) * P.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
         const double sh = P.shift_u != 0.0 ? (double)shift_off<Q, double>(i, P.rho0, P.shift_u) : 0.0;
-        A[opp<Q>(i) * N + cell] = SS::st((T)(fd - sh));
+        A[pidx<Q>(P.nx, opp<Q>(i), x, row)] = SS::st((T)(fd - sh));
     });
     T *u_0 = (T *)P.u[0], *us = (T *)P.usnap;
     for (int a = 0; a < D; ++a) {
@@ -702,7 +721,7 @@ __device__ __forceinline__ void serve_cells(const KP &P, int rd, T (*xch)[SERVE_
     if (PLATE) {
         // outlet: the incoming populations of column nx-2 before anyone writes
         for (int y = threadIdx.x; y < P.ny; y += SBLK) {
-            const Cell Cn = make_cell<true>(P, nx - 2, y, 0, true);
+            const Cell Cn = make_cell<9, true>(P, nx - 2, y, 0, true);
             T g[9];
             gather<9, S, T, ODD, true, HRFD>(P, Cn, g);
             xch[0][y] = g[2];
@@ -713,7 +732,7 @@ __device__ __forceinline__ void serve_cells(const KP &P, int rd, T (*xch)[SERVE_
     }
     for (int64_t cell = threadIdx.x; cell < N; cell += SBLK) {
         const int y = (int)(cell / nx), x = (int)(cell - (int64_t)y * nx);
-        const Cell C = make_cell<PLATE>(P, x, y, 0, true);
+        const Cell C = make_cell<9, PLATE>(P, x, y, 0, true);
         T f[9];
         gather<9, S, T, ODD, PLATE, HRFD>(P, C, f);
         if (PLATE) {
