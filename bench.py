@@ -90,9 +90,14 @@ def serving_bench(args):
     nseq = len(reqs) if args.seq_requests < 0 else min(args.seq_requests, len(reqs))
     seq = reqs[:nseq]
     res_s, sum_s = serving.run_sequential(seq, tol=args.tol, max_steps=args.max_steps, log=log)
-    # same requests, same result: step counts and end status must agree
+    # same requests, same result: step counts and end status must agree, and
+    # the mean u_tau at the end (FP32 fields; the two paths differ only in the
+    # order of FP64 sums and in FMA contraction)
     agree = all(res_b[r["id"]]["status"] == res_s[r["id"]]["status"] and
                 res_b[r["id"]]["steps"] == res_s[r["id"]]["steps"] for r in seq)
+    dut = [abs(res_b[r["id"]]["mean_u_tau"] - res_s[r["id"]]["mean_u_tau"]) /
+           max(abs(res_s[r["id"]]["mean_u_tau"]), 1e-300) for r in seq
+           if res_s[r["id"]]["status"] != 4 and res_b[r["id"]]["status"] != 4]
     out = {
         "metric": "batched solves/s (p99 time-to-result reported) vs sequential plain solves",
         "value": round(sum_b["solves_per_s"], 3),
@@ -117,6 +122,7 @@ def serving_bench(args):
         "speedup_solves_per_s": sum_b["solves_per_s"] / sum_s["solves_per_s"]
                                 if nseq and sum_s["solves_per_s"] > 0 else None,
         "same_steps_and_status": agree,
+        "max_rel_diff_mean_u_tau": max(dut) if dut else None,
     }
     print(json.dumps(out), flush=True)
 
@@ -141,7 +147,7 @@ def main():
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--max-steps", type=int, default=20000)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--chunk", type=int, default=500)
+    ap.add_argument("--chunk", type=int, default=200)
     ap.add_argument("--seq-requests", type=int, default=-1,
                     help="requests run sequentially (default: all)")
     args = ap.parse_args()

@@ -247,13 +247,19 @@ int lbm_destroy(lbm_t *h);
  * Serving pool: many independent solves resident in one device buffer.
  *
  * Requests are admitted by footprint (first fit in the pool buffer) and
- * advanced together.  Small D2Q9 lattices (<= 65536 cells; plates with
- * ny <= 256) are advanced by one persistent launch in which each lattice is
- * owned by one workgroup that loops over the steps; larger lattices run the
- * regular kernels on a second stream, so both kinds overlap on the device.
- * Every lattice stops on convergence (residual of lbm_residual_t below `tol`
- * at a reduction step), divergence or `max_steps`.  Results of one lattice do
- * not depend on what else is resident.
+ * advanced together in two groups that overlap on the device:
+ *  - small D2Q9 lattices (<= 2048 cells, channels <= 4096) on the caller's
+ *    stream: one persistent launch per kind (storage, collision, flow, wall
+ *    treatment) in which each lattice is owned by one workgroup that loops
+ *    over the steps;
+ *  - every other lattice on a second stream: each phase of a step (fused
+ *    update, wall function, residual) is one launch over all resident
+ *    lattices of a kind, whatever their number.
+ * Every lattice stops on the device on convergence (residual of
+ * lbm_residual_t below `tol` at a reduction step), divergence or `max_steps`.
+ * Results of one lattice do not depend on what else is resident.  The device
+ * buffer also holds the slot descriptors, slot lists and block tables (about
+ * 1/2000 of its size); the pool allocates a few pinned host pages.
  * ------------------------------------------------------------------------- */
 typedef struct lbm_pool lbm_pool_t;
 
@@ -286,14 +292,22 @@ int lbm_pool_admit(lbm_pool_t *pool, lbm_lattice_t lattice, int nx, int ny, int 
 /* Advances every running slot by up to `steps` steps and synchronizes. */
 int lbm_pool_step(lbm_pool_t *pool, int64_t steps);
 
-/* Status of one slot (host data refreshed by lbm_pool_step). */
+/* Continuous batching without blocking: for each group whose previous chunk
+ * has finished, refreshes its slots' status and launches the next chunk of
+ * `steps` steps for its running slots (slots admitted since are included);
+ * returns at once.  *in_flight (may be NULL) receives the number of groups
+ * (0-2) with a chunk on the device. */
+int lbm_pool_pump(lbm_pool_t *pool, int64_t steps, int *in_flight);
+
+/* Status of one slot (host data refreshed by lbm_pool_step / lbm_pool_pump). */
 int lbm_pool_poll(lbm_pool_t *pool, int slot, lbm_pool_status_t *out);
 
 /* The slot's lattice handle, for lbm_moments / lbm_wall / lbm_populations
  * (valid until lbm_pool_release); NULL for a bad slot. */
 lbm_t *lbm_pool_lattice(lbm_pool_t *pool, int slot);
 
-/* Frees the slot and its memory (synchronizes). */
+/* Frees the slot and its memory; if its group has a chunk on the device the
+ * memory is returned when that chunk is harvested (the slot is gone at once). */
 int lbm_pool_release(lbm_pool_t *pool, int slot);
 
 /* Releases every slot and the pool's host state and stream; the buffer stays

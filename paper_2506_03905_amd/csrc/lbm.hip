@@ -363,6 +363,48 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f)
 }
 
 // ---------------------------------------------------------------------------
+// cell_update: one fused LBM-RANS step of the cell (x, y, z) by one thread of
+// a BLK-thread block.  Plate blocks must be aligned to the right end of a row
+// (columns nx-2 and nx-1 in one block) for the outlet exchange through LDS.
+// ---------------------------------------------------------------------------
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC>
+__device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, int z, bool active)
+{
+    const int nx = P.nx;
+    const int tid = threadIdx.x;
+    const Cell C = make_cell<Q, PLATE>(P, x, y, z, active);
+    T f[Q];
+    if (active) gather<Q, S, T, ODD, PLATE, HRFD>(P, C, f);
+    if (PLATE) {
+        // outlet: unknown populations copied from column nx-2 (through LDS)
+        __shared__ T xch[3][BLK];
+        if (active && x == nx - 2) {
+            xch[0][tid] = f[2];
+            xch[1][tid] = f[6];
+            xch[2][tid] = f[8];
+        }
+        __syncthreads();
+        if (active && x == nx - 1) {
+            f[2] = xch[0][tid - 1];
+            f[6] = xch[1][tid - 1];
+            f[8] = xch[2][tid - 1];
+        }
+        if (active && x == 0) zou_he(P, f);
+    }
+    if (!active) return;
+    finish<Q, S, T, ODD, PLATE, HRFD, CMC>(P, C, rd, f);
+}
+
+// plate mapping: rows aligned to the right end, nseg blocks per row
+__device__ __forceinline__ void plate_block(int nx, int64_t b, int tid, int &x, int &y)
+{
+    const int nseg = (nx + BLK - 1) / BLK;
+    const int row = (int)(b / nseg), seg = (int)(b - (int64_t)row * nseg);
+    x = nx - (nseg - seg) * BLK + tid;
+    y = row;
+}
+
+// ---------------------------------------------------------------------------
 // k_step: one fused LBM-RANS step, one thread per cell.
 // ---------------------------------------------------------------------------
 template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC>
@@ -393,34 +435,11 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         z = (int)(r / ny);
     } else {
         // rows aligned to the right end so that columns nx-2 and nx-1 share a block
-        const int nseg = (nx + BLK - 1) / BLK;
-        const int row = blockIdx.x / nseg, seg = blockIdx.x - row * nseg;
-        x = nx - (nseg - seg) * BLK + tid;
-        y = row;
+        plate_block(nx, blockIdx.x, tid, x, y);
         z = 0;
         active = x >= 0;
     }
-    const Cell C = make_cell<Q, PLATE>(P, x, y, z, active);
-    T f[Q];
-    if (active) gather<Q, S, T, ODD, PLATE, HRFD>(P, C, f);
-    if (PLATE) {
-        // outlet: unknown populations copied from column nx-2 (through LDS)
-        __shared__ T xch[3][BLK];
-        if (active && x == nx - 2) {
-            xch[0][tid] = f[2];
-            xch[1][tid] = f[6];
-            xch[2][tid] = f[8];
-        }
-        __syncthreads();
-        if (active && x == nx - 1) {
-            f[2] = xch[0][tid - 1];
-            f[6] = xch[1][tid - 1];
-            f[8] = xch[2][tid - 1];
-        }
-        if (active && x == 0) zou_he(P, f);
-    }
-    if (!active) return;
-    finish<Q, S, T, ODD, PLATE, HRFD, CMC>(P, C, rd, f);
+    cell_update<Q, S, T, ODD, PLATE, HRFD, CMC>(P, rd, x, y, z, active);
 }
 
 // ---------------------------------------------------------------------------
@@ -632,19 +651,21 @@ __global__ void k_init_wall(KP P)
 // slots: 0 sum(rho - rho0), 1-3 sum(rho u), 4 sum |u - usnap|^2, 5 sum |u|^2,
 // 6 bad-value count.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void block_sum(double (*sh)[BLK], double *v, int nv)
+template <int NT> __device__ __forceinline__ void block_sum(double (*sh)[NT], double *v, int nv)
 {
     const int t = threadIdx.x;
     for (int k = 0; k < nv; ++k) sh[k][t] = v[k];
     __syncthreads();
-    for (int s = BLK / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (t < s)
             for (int k = 0; k < nv; ++k) sh[k][t] += sh[k][t + s];
         __syncthreads();
     }
 }
 
-template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) k_reduce(KP P, bool odd_state, int cur)
+// Block b of nb: FP64 partial sums (slots 0-7) over its share of the cells,
+// written to P.partials[b]; the velocity snapshot is refreshed on the way.
+template <int Q, typename S, typename T> __device__ __forceinline__ void reduce_part(const KP &P, bool odd_state, int cur, int b, int nb)
 {
     constexpr int D = Lat<Q>::D;
     __shared__ double sh[8][BLK];
@@ -653,7 +674,7 @@ template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) 
     const S *A = (const S *)P.pops;
     const T *uc = (const T *)P.u[cur];
     T *us = (T *)P.usnap;
-    for (int64_t cell = (int64_t)blockIdx.x * BLK + threadIdx.x; cell < N; cell += (int64_t)gridDim.x * BLK) {
+    for (int64_t cell = (int64_t)b * BLK + threadIdx.x; cell < N; cell += (int64_t)nb * BLK) {
         const int64_t r = cell / P.nx;
         const int x = (int)(cell - r * P.nx), y = (int)(r % P.ny), z = (int)(r / P.ny);
         double drho = 0.0;
@@ -676,11 +697,16 @@ template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) 
         acc[6] += bad ? 1.0 : 0.0;
     }
     // slot 7: this block's share of the wall cells' u_tau
-    for (int64_t w = (int64_t)blockIdx.x * BLK + threadIdx.x; w < P.nwall; w += (int64_t)gridDim.x * BLK)
+    for (int64_t w = (int64_t)b * BLK + threadIdx.x; w < P.nwall; w += (int64_t)nb * BLK)
         acc[7] += P.utau[w];
-    block_sum(sh, acc, 8);
+    block_sum<BLK>(sh, acc, 8);
     if (threadIdx.x == 0)
-        for (int k = 0; k < 8; ++k) P.partials[blockIdx.x * NRED + k] = sh[k][0];
+        for (int k = 0; k < 8; ++k) P.partials[b * NRED + k] = sh[k][0];
+}
+
+template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) k_reduce(KP P, bool odd_state, int cur)
+{
+    reduce_part<Q, S, T>(P, odd_state, cur, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(BLK) k_reduce_final(KP P, int nblocks, int slot)
@@ -689,29 +715,54 @@ __global__ void __launch_bounds__(BLK) k_reduce_final(KP P, int nblocks, int slo
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblocks; b += BLK)
         for (int k = 0; k < 8; ++k) acc[k] += P.partials[b * NRED + k];
-    block_sum(sh, acc, 8);
+    block_sum<BLK>(sh, acc, 8);
     if (threadIdx.x == 0)
         for (int k = 0; k < 8; ++k) P.result[slot * NRED + k] = sh[k][0];
 }
 
 // ---------------------------------------------------------------------------
-// Serving: persistent kernel over many small D2Q9 lattices, one workgroup per
-// lattice.  Each workgroup loops over time steps with barriers between the
-// phases of a step (fused cell update, wall function, periodic residual) and
-// stops its lattice on convergence, divergence or the step cap.  Every cell
-// update is the same gather/finish code as k_step.
+// Serving.  Small D2Q9 lattices: a persistent kernel, one workgroup per
+// lattice, loops over time steps with barriers between the phases of a step
+// (fused cell update, wall function, periodic residual).  Large lattices: each
+// phase of a step is one launch over every resident lattice of a kind, a
+// table mapping each block to (slot, block of that slot).  Both stop a
+// lattice on convergence, divergence or its step cap, on the device, with
+// the same cell update code as k_step.
 // ---------------------------------------------------------------------------
-constexpr int SBLK = 256;
+constexpr int SBLK = 512;
 constexpr int SERVE_MAX_NY = 256;  // plate rows held in the outlet exchange buffer
+constexpr int MRED = 128;          // reduction blocks per large lattice
 
 enum { SLOT_IDLE = 0, SLOT_RUNNING = 1, SLOT_CONVERGED = 2, SLOT_CAPPED = 3, SLOT_DIVERGED = 4 };
 
 struct SlotDesc {
     KP kp;
-    int64_t step, max_steps, snap_step;
+    int64_t step;       // steps done (large lattices: at the start of the chunk)
+    int64_t max_steps;  // step cap
+    int64_t snap_step;  // step of the previous residual snapshot
+    int64_t stop_step;  // step at which the lattice stopped
     double tol, residual, mean_utau;
     int status, reduce_every, variant, pad_;
 };
+
+// residual r = ||u - u_snap|| / (K ||u||), mean u_tau and the stop decision
+// from the FP64 sums {du^2, u^2, non-finite count, sum u_tau}; thread 0 only.
+__device__ __forceinline__ void slot_verdict(SlotDesc &SD, int64_t nwall, int64_t step, double du2, double uu,
+                                             double bad, double sutau, bool red_now)
+{
+    const double K = (double)(step - SD.snap_step);
+    const double r = uu > 0.0 ? sqrt(du2) / (K * sqrt(uu)) : 0.0;
+    SD.residual = r;
+    SD.mean_utau = nwall > 0 ? sutau / (double)nwall : 0.0;
+    SD.snap_step = step;
+    if (bad > 0.0 || !isfinite(r))
+        SD.status = SLOT_DIVERGED;
+    else if (red_now && r < SD.tol)
+        SD.status = SLOT_CONVERGED;
+    else if (step >= SD.max_steps)
+        SD.status = SLOT_CAPPED;
+    if (SD.status != SLOT_RUNNING) SD.stop_step = step;
+}
 
 template <typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC>
 __device__ __forceinline__ void serve_cells(const KP &P, int rd, T (*xch)[SERVE_MAX_NY])
@@ -747,15 +798,18 @@ __device__ __forceinline__ void serve_cells(const KP &P, int rd, T (*xch)[SERVE_
     }
 }
 
+// P: the lattice's parameters copied to LDS (the descriptor itself is
+// written by the kernel, so reading it from global memory would reload every
+// field after every store)
 template <typename S, typename T, bool PLATE, bool HRFD, bool CMC>
-__device__ void serve_loop(SlotDesc &SD, int chunk)
+__device__ void serve_loop(SlotDesc &SD, const KP &P, int chunk)
 {
-    const KP &P = SD.kp;
     __shared__ T xch[3][SERVE_MAX_NY];
-    __shared__ double red[8][BLK];
+    __shared__ double red[4][SBLK];
     __shared__ int stop;
     int64_t step = SD.step;
-    const int64_t N = P.ncell;
+    const int64_t N = P.ncell, max_steps = SD.max_steps;
+    const int reduce_every = SD.reduce_every;
     if (threadIdx.x == 0) stop = 0;
     __syncthreads();
     for (int s = 0; s < chunk; ++s) {
@@ -768,12 +822,11 @@ __device__ void serve_loop(SlotDesc &SD, int chunk)
         for (int64_t w = threadIdx.x; w < P.nwall; w += SBLK) wall_cell<2, T>(P, w, rd ^ 1);
         __syncthreads();
         ++step;
-        const bool red_now = SD.reduce_every > 0 && step % SD.reduce_every == 0;
-        if (red_now || step >= SD.max_steps) {
-            // residual ||u - u_snap|| / (K ||u||), mean u_tau, NaN check (FP64, fixed order)
+        const bool red_now = reduce_every > 0 && step % reduce_every == 0;
+        if (red_now || step >= max_steps) {
             const T *uc = (const T *)P.u[step & 1];
             T *us = (T *)P.usnap;
-            double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            double acc[4] = {0, 0, 0, 0};
             for (int64_t cell = threadIdx.x; cell < N; cell += SBLK) {
                 for (int a = 0; a < 2; ++a) {
                     const double ua = (double)uc[a * N + cell], d = ua - (double)us[a * N + cell];
@@ -784,23 +837,10 @@ __device__ void serve_loop(SlotDesc &SD, int chunk)
                 }
             }
             for (int64_t w = threadIdx.x; w < P.nwall; w += SBLK) acc[3] += P.utau[w];
-            block_sum(red, acc, 4);
+            block_sum<SBLK>(red, acc, 4);
             if (threadIdx.x == 0) {
-                const double K = (double)(step - SD.snap_step);
-                const double r = red[1][0] > 0.0 ? sqrt(red[0][0]) / (K * sqrt(red[1][0])) : 0.0;
-                SD.residual = r;
-                SD.mean_utau = P.nwall > 0 ? red[3][0] / (double)P.nwall : 0.0;
-                SD.snap_step = step;
-                if (red[2][0] > 0.0 || !isfinite(r)) {
-                    SD.status = SLOT_DIVERGED;
-                    stop = 1;
-                } else if (red_now && r < SD.tol) {
-                    SD.status = SLOT_CONVERGED;
-                    stop = 1;
-                } else if (step >= SD.max_steps) {
-                    SD.status = SLOT_CAPPED;
-                    stop = 1;
-                }
+                slot_verdict(SD, P.nwall, step, red[0][0], red[1][0], red[2][0], red[3][0], red_now);
+                stop = SD.status != SLOT_RUNNING;
             }
             __syncthreads();
             if (stop) break;
@@ -809,17 +849,127 @@ __device__ void serve_loop(SlotDesc &SD, int chunk)
     if (threadIdx.x == 0) SD.step = step;
 }
 
-template <typename S, typename T, bool CMC> __global__ void __launch_bounds__(SBLK) k_serve(SlotDesc *slots, int variant, int chunk)
+// one workgroup per listed small lattice of one kind (storage, collision,
+// flow, wall treatment)
+template <typename S, typename T, bool CMC, bool PLATE, bool HRFD>
+__global__ void __launch_bounds__(SBLK) k_serve(SlotDesc *slots, const int *list, int chunk)
 {
-    SlotDesc &SD = slots[blockIdx.x];
-    if (SD.status != SLOT_RUNNING || SD.variant != variant) return;
-    const bool plate = SD.kp.flow == FLOW_PLATE, hrfd = SD.kp.scheme >= WALL_HRFD;
-    if (plate) {
-        if (hrfd) serve_loop<S, T, true, true, CMC>(SD, chunk);
-        else serve_loop<S, T, true, false, CMC>(SD, chunk);
+    static_assert(sizeof(KP) % 8 == 0 && sizeof(KP) / 8 <= SBLK, "KP copy");
+    __shared__ KP sP;
+    SlotDesc &SD = slots[list[blockIdx.x]];
+    if (SD.status != SLOT_RUNNING) return;
+    if (threadIdx.x < sizeof(KP) / 8) ((int64_t *)&sP)[threadIdx.x] = ((const int64_t *)&SD.kp)[threadIdx.x];
+    __syncthreads();
+    serve_loop<S, T, PLATE, HRFD, CMC>(SD, sP, chunk);
+}
+
+// ---- large lattices: one launch per phase over all lattices of a kind -----
+// tab[b] = (slot, block of that slot); s = step within the chunk.
+__device__ __forceinline__ bool mslot(const SlotDesc *slots, int slot, int s, int64_t &step)
+{
+    const SlotDesc &SD = slots[slot];
+    step = SD.step + s;
+    return SD.status == SLOT_RUNNING && step < SD.max_steps;
+}
+
+template <int Q, typename S, typename T, bool ODD, bool CMC>
+__device__ __forceinline__ void mstep_body(const KP &P, int rd, int64_t lb)
+{
+    const int tid = threadIdx.x;
+    if (P.flow == FLOW_PLATE) {
+        if constexpr (Q == 9) {
+            int x, y;
+            plate_block(P.nx, lb, tid, x, y);
+            if (P.scheme >= WALL_HRFD)
+                cell_update<Q, S, T, ODD, true, true, CMC>(P, rd, x, y, 0, x >= 0);
+            else
+                cell_update<Q, S, T, ODD, true, false, CMC>(P, rd, x, y, 0, x >= 0);
+        }
+        return;
+    }
+    const int64_t cell = lb * BLK + tid;
+    const bool active = cell < P.ncell;
+    const int64_t r = active ? cell / P.nx : 0;
+    const int x = active ? (int)(cell - r * P.nx) : 0, y = (int)(r % P.ny), z = (int)(r / P.ny);
+    if constexpr (Q == 9) {
+        if (P.scheme >= WALL_HRFD) {
+            cell_update<Q, S, T, ODD, false, true, CMC>(P, rd, x, y, z, active);
+            return;
+        }
+    }
+    cell_update<Q, S, T, ODD, false, false, CMC>(P, rd, x, y, z, active);
+}
+
+template <int Q, typename S, typename T, bool CMC>
+__global__ void __launch_bounds__(BLK) k_mstep(const SlotDesc *__restrict__ slots, const int2 *__restrict__ tab, int s)
+{
+    const int2 e = tab[blockIdx.x];
+    int64_t step;
+    if (!mslot(slots, e.x, s, step)) return;
+    const KP &P = slots[e.x].kp;
+    const int rd = (int)(step & 1);
+    if ((step + 1) & 1)
+        mstep_body<Q, S, T, true, CMC>(P, rd, e.y);
+    else
+        mstep_body<Q, S, T, false, CMC>(P, rd, e.y);
+}
+
+template <int D, typename T> __global__ void __launch_bounds__(BLK) k_mwall(const SlotDesc *__restrict__ slots, const int2 *__restrict__ tab, int s)
+{
+    const int2 e = tab[blockIdx.x];
+    int64_t step;
+    if (!mslot(slots, e.x, s, step)) return;
+    const KP &P = slots[e.x].kp;
+    const int64_t w = (int64_t)e.y * BLK + threadIdx.x;
+    if (w < P.nwall) wall_cell<D, T>(P, w, (int)(step & 1) ^ 1);
+}
+
+// residual due after step `step` (the cap included)?
+__device__ __forceinline__ bool mdue(const SlotDesc &SD, int64_t after, bool &red_now)
+{
+    red_now = SD.reduce_every > 0 && after % SD.reduce_every == 0;
+    return red_now || after >= SD.max_steps;
+}
+
+template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) k_mreduce(const SlotDesc *__restrict__ slots, const int *__restrict__ list, int s)
+{
+    const int slot = list[blockIdx.x / MRED], b = blockIdx.x % MRED;
+    int64_t step;
+    if (!mslot(slots, slot, s, step)) return;
+    bool red_now;
+    if (!mdue(slots[slot], step + 1, red_now)) return;
+    const int cur = (int)((step + 1) & 1);
+    reduce_part<Q, S, T>(slots[slot].kp, cur != 0, cur, b, MRED);
+}
+
+__global__ void __launch_bounds__(BLK) k_mreduce_final(SlotDesc *slots, const int *list, int s)
+{
+    const int slot = list[blockIdx.x];
+    int64_t step;
+    if (!mslot(slots, slot, s, step)) return;
+    SlotDesc &SD = slots[slot];
+    bool red_now;
+    if (!mdue(SD, step + 1, red_now)) return;
+    __shared__ double sh[8][BLK];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < MRED; b += BLK)
+        for (int k = 0; k < 8; ++k) acc[k] += SD.kp.partials[b * NRED + k];
+    block_sum<BLK>(sh, acc, 8);
+    // slots: 4 = sum du^2, 5 = sum u^2, 6 = bad cells, 7 = sum u_tau
+    if (threadIdx.x == 0) slot_verdict(SD, SD.kp.nwall, step + 1, sh[4][0], sh[5][0], sh[6][0], sh[7][0], red_now);
+}
+
+// end of a chunk: steps done by every listed lattice
+__global__ void k_mfinish(SlotDesc *slots, const int *list, int n, int chunk)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    SlotDesc &SD = slots[list[i]];
+    if (SD.status == SLOT_RUNNING) {
+        SD.step += chunk;
+        if (SD.step > SD.max_steps) SD.step = SD.max_steps;
     } else {
-        if (hrfd) serve_loop<S, T, false, true, CMC>(SD, chunk);
-        else serve_loop<S, T, false, false, CMC>(SD, chunk);
+        SD.step = SD.stop_step;
     }
 }
 
@@ -1498,28 +1648,57 @@ const char *lbm_last_error(void) { return g_err; }
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int64_t SERVE_SMALL_CELLS = 65536;
+// D2Q9 lattices up to SERVE_SMALL_CELLS cells (channels up to
+// SERVE_SMALL_CHANNEL) run in the persistent launch, where a step of a lattice
+// takes a few microseconds whatever else is resident; larger ones go to the
+// multi-lattice launches, whose step time grows with the total resident work.
+constexpr int64_t SERVE_SMALL_CELLS = 4 * SBLK, SERVE_SMALL_CHANNEL = 8 * SBLK;
 
 struct PoolSlot {
-    bool used = false, small = false;
+    bool used = false, small = false, releasing = false;
     lbm *h = nullptr;
     int64_t off = 0, bytes = 0;
     int status = SLOT_IDLE;
-    double tol = 0.0, residual = 0.0, mean_utau = 0.0;
-    int64_t max_steps = 0;
+    int key = 0;  // launch kind: see slot_key
+    double residual = 0.0, mean_utau = 0.0;
+    int64_t steps = 0, max_steps = 0, reduce_every = 100;
+    int64_t step_blocks = 0, wall_blocks = 0;
 };
 
-int variant_of(const lbm_params_t &p) { return p.precision * 2 + (p.collision == LBM_COLL_CM ? 1 : 0); }
+// small: precision x collision x flow x wall treatment (32 kinds);
+// large: lattice x precision x collision (16 kinds)
+int slot_key(const lbm *h, bool small)
+{
+    const int v = h->p.precision * 2 + (h->p.collision == LBM_COLL_CM ? 1 : 0);
+    if (small) return v * 4 + (h->p.flow == LBM_FLOW_PLATE ? 2 : 0) + (h->p.scheme >= LBM_WALL_HRFD ? 1 : 0);
+    return (h->Q == 19 ? 8 : 0) + v;
+}
+constexpr int NKEY = 16, NSKEY = 32;
+
+struct PoolGroup {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool in_flight = false;
+    SlotDesc *mirror = nullptr;    // pinned: descriptors copied back at the end of a chunk
+    int *hlist = nullptr;          // pinned staging of the slot lists
+    int64_t *hpref = nullptr;      // pinned staging of the block prefix sums (large group)
+    std::vector<int> chunk_slots;  // slots running when the chunk was launched
+};
 
 }  // namespace
 
 struct lbm_pool {
     char *base;
-    int64_t bytes, desc_bytes;
+    int64_t bytes, data_off;
     int max_slots;
-    hipStream_t sA, sB;
-    SlotDesc *dslots;
-    std::vector<SlotDesc> hslots;
+    bool own_sA;
+    SlotDesc *dslots;       // device descriptors
+    SlotDesc *hstage;       // pinned staging of descriptor uploads
+    int *dlist;             // device slot lists: [0, M) small group, [M, 3M) large group
+    int64_t *dpref;         // device block prefix sums (2 (M + 1))
+    int2 *dtab;             // device block tables: cells [0, tab_cap), walls [tab_cap, 2 tab_cap)
+    int64_t tab_cap, tab_used_step, tab_used_wall;
+    PoolGroup g[2];         // 0: persistent small-lattice launches, 1: large lattices
     std::vector<PoolSlot> slots;
     std::map<int64_t, int64_t> freel;  // offset -> size
 };
@@ -1558,23 +1737,247 @@ void pool_free(lbm_pool *pl, int64_t off, int64_t bytes)
     }
 }
 
-template <typename S, typename T, bool CMC> int launch_serve(lbm_pool *pl, int variant, int chunk)
+// ---- launches -------------------------------------------------------------
+template <typename S, typename T, bool CMC> int launch_serve(lbm_pool *pl, int fw, const int *dlist, int n, int chunk)
 {
-    hipLaunchKernelGGL((k_serve<S, T, CMC>), dim3(pl->max_slots), dim3(SBLK), 0, pl->sA, pl->dslots, variant, chunk);
+    hipStream_t st = pl->g[0].stream;
+    SlotDesc *d = pl->dslots;
+    switch (fw) {
+    case 0: hipLaunchKernelGGL((k_serve<S, T, CMC, false, false>), dim3(n), dim3(SBLK), 0, st, d, dlist, chunk); break;
+    case 1: hipLaunchKernelGGL((k_serve<S, T, CMC, false, true>), dim3(n), dim3(SBLK), 0, st, d, dlist, chunk); break;
+    case 2: hipLaunchKernelGGL((k_serve<S, T, CMC, true, false>), dim3(n), dim3(SBLK), 0, st, d, dlist, chunk); break;
+    default: hipLaunchKernelGGL((k_serve<S, T, CMC, true, true>), dim3(n), dim3(SBLK), 0, st, d, dlist, chunk); break;
+    }
     HIPCHK(hipGetLastError());
     return LBM_OK;
 }
 
-int serve_variant(lbm_pool *pl, int variant, int chunk)
+int serve_key(lbm_pool *pl, int key, const int *dlist, int n, int chunk)
 {
-    const int prec = variant / 2;
-    const bool cm = variant & 1;
-    switch (prec) {
-    case LBM_F64: return cm ? launch_serve<double, double, true>(pl, variant, chunk) : launch_serve<double, double, false>(pl, variant, chunk);
-    case LBM_F32: return cm ? launch_serve<float, float, true>(pl, variant, chunk) : launch_serve<float, float, false>(pl, variant, chunk);
-    case LBM_F16: return cm ? launch_serve<_Float16, float, true>(pl, variant, chunk) : launch_serve<_Float16, float, false>(pl, variant, chunk);
-    default: return cm ? launch_serve<bf16s, float, true>(pl, variant, chunk) : launch_serve<bf16s, float, false>(pl, variant, chunk);
+    const int fw = key & 3, v = key >> 2;
+    const bool cm = v & 1;
+    switch (v / 2) {
+    case LBM_F64: return cm ? launch_serve<double, double, true>(pl, fw, dlist, n, chunk) : launch_serve<double, double, false>(pl, fw, dlist, n, chunk);
+    case LBM_F32: return cm ? launch_serve<float, float, true>(pl, fw, dlist, n, chunk) : launch_serve<float, float, false>(pl, fw, dlist, n, chunk);
+    case LBM_F16: return cm ? launch_serve<_Float16, float, true>(pl, fw, dlist, n, chunk) : launch_serve<_Float16, float, false>(pl, fw, dlist, n, chunk);
+    default: return cm ? launch_serve<bf16s, float, true>(pl, fw, dlist, n, chunk) : launch_serve<bf16s, float, false>(pl, fw, dlist, n, chunk);
     }
+}
+
+struct MLaunch {
+    int64_t step_off, step_n, wall_off, wall_n;
+    const int *list;
+    int nlist;
+    int s;
+};
+
+template <int Q, typename S, typename T, bool CMC> struct MKind {
+    static int step(lbm_pool *pl, const MLaunch &m)
+    {
+        hipStream_t st = pl->g[1].stream;
+        if (m.step_n > 0) hipLaunchKernelGGL((k_mstep<Q, S, T, CMC>), dim3((unsigned)m.step_n), dim3(BLK), 0, st, pl->dslots, pl->dtab + m.step_off, m.s);
+        if (m.wall_n > 0) hipLaunchKernelGGL((k_mwall<Lat<Q>::D, T>), dim3((unsigned)m.wall_n), dim3(BLK), 0, st, pl->dslots, pl->dtab + pl->tab_cap + m.wall_off, m.s);
+        HIPCHK(hipGetLastError());
+        return LBM_OK;
+    }
+    static int reduce(lbm_pool *pl, const MLaunch &m)
+    {
+        hipStream_t st = pl->g[1].stream;
+        hipLaunchKernelGGL((k_mreduce<Q, S, T>), dim3((unsigned)(m.nlist * MRED)), dim3(BLK), 0, st, pl->dslots, m.list, m.s);
+        hipLaunchKernelGGL(k_mreduce_final, dim3((unsigned)m.nlist), dim3(BLK), 0, st, pl->dslots, m.list, m.s);
+        HIPCHK(hipGetLastError());
+        return LBM_OK;
+    }
+};
+
+template <int Q> int mdispatch(lbm_pool *pl, int v, const MLaunch &m, bool red)
+{
+    const bool cm = v & 1;
+#define LBM_MK(S_, T_)                                                                       \
+    return cm ? (red ? MKind<Q, S_, T_, true>::reduce(pl, m) : MKind<Q, S_, T_, true>::step(pl, m)) \
+              : (red ? MKind<Q, S_, T_, false>::reduce(pl, m) : MKind<Q, S_, T_, false>::step(pl, m))
+    switch (v / 2) {
+    case LBM_F64: LBM_MK(double, double);
+    case LBM_F32: LBM_MK(float, float);
+    case LBM_F16: LBM_MK(_Float16, float);
+    default: LBM_MK(bf16s, float);
+    }
+#undef LBM_MK
+}
+
+int mlaunch(lbm_pool *pl, int key, const MLaunch &m, bool red)
+{
+    return key >= 8 ? mdispatch<19>(pl, key - 8, m, red) : mdispatch<9>(pl, key, m, red);
+}
+
+__global__ void k_mtab(int2 *tab, const int64_t *pref, const int *slots, int n)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i >= pref[n]) return;
+    int lo = 0, hi = n - 1;  // largest k with pref[k] <= i
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (pref[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    tab[i] = make_int2(slots[lo], (int)(i - pref[lo]));
+}
+
+// ---- group bookkeeping -------------------------------------------------------
+void finish_release(lbm_pool *pl, int i)
+{
+    PoolSlot &S = pl->slots[i];
+    if (!S.small) {
+        pl->tab_used_step -= S.step_blocks;
+        pl->tab_used_wall -= S.wall_blocks;
+    }
+    lbm_destroy(S.h);
+    pool_free(pl, S.off, S.bytes);
+    S = PoolSlot{};
+}
+
+void harvest(lbm_pool *pl, int gi)
+{
+    PoolGroup &G = pl->g[gi];
+    for (int i : G.chunk_slots) {
+        PoolSlot &S = pl->slots[i];
+        if (!S.used) continue;
+        const SlotDesc &d = G.mirror[i];
+        S.status = d.status;
+        S.residual = d.residual;
+        S.mean_utau = d.mean_utau;
+        S.steps = d.step;
+        S.h->step = d.step;
+        S.h->last_reduce_step = -1;
+    }
+    G.in_flight = false;
+    for (int i = 0; i < pl->max_slots; ++i) {
+        PoolSlot &S = pl->slots[i];
+        if (S.used && S.releasing && (S.small ? 0 : 1) == gi) finish_release(pl, i);
+    }
+}
+
+int launch_small(lbm_pool *pl, int chunk)
+{
+    PoolGroup &G = pl->g[0];
+    G.chunk_slots.clear();
+    int start[NSKEY], cnt[NSKEY], n = 0;
+    for (int k = 0; k < NSKEY; ++k) {
+        start[k] = n;
+        for (int i = 0; i < pl->max_slots; ++i) {
+            const PoolSlot &S = pl->slots[i];
+            if (S.used && !S.releasing && S.small && S.status == SLOT_RUNNING && S.key == k) {
+                G.hlist[n++] = i;
+                G.chunk_slots.push_back(i);
+            }
+        }
+        cnt[k] = n - start[k];
+    }
+    if (n == 0) return LBM_OK;
+    HIPCHK(hipMemcpyAsync(pl->dlist, G.hlist, sizeof(int) * n, hipMemcpyHostToDevice, G.stream));
+    for (int k = 0; k < NSKEY; ++k)
+        if (cnt[k]) {
+            int rc = serve_key(pl, k, pl->dlist + start[k], cnt[k], chunk);
+            if (rc) return rc;
+        }
+    HIPCHK(hipMemcpyAsync(G.mirror, pl->dslots, sizeof(SlotDesc) * pl->max_slots, hipMemcpyDeviceToHost, G.stream));
+    HIPCHK(hipEventRecord(G.done, G.stream));
+    G.in_flight = true;
+    return LBM_OK;
+}
+
+int launch_large(lbm_pool *pl, int chunk)
+{
+    PoolGroup &G = pl->g[1];
+    const int M = pl->max_slots;
+    G.chunk_slots.clear();
+    int lstart[NKEY], lcnt[NKEY], n = 0;
+    int64_t soff[NKEY], scnt[NKEY], woff[NKEY], wcnt[NKEY];
+    int64_t *ps = G.hpref, *pw = G.hpref + (M + 1);
+    ps[0] = pw[0] = 0;
+    for (int k = 0; k < NKEY; ++k) {
+        lstart[k] = n;
+        soff[k] = ps[n];
+        woff[k] = pw[n];
+        for (int i = 0; i < M; ++i) {
+            const PoolSlot &S = pl->slots[i];
+            if (S.used && !S.releasing && !S.small && S.status == SLOT_RUNNING && S.key == k) {
+                G.hlist[n] = i;
+                ps[n + 1] = ps[n] + S.step_blocks;
+                pw[n + 1] = pw[n] + S.wall_blocks;
+                ++n;
+                G.chunk_slots.push_back(i);
+            }
+        }
+        lcnt[k] = n - lstart[k];
+        scnt[k] = ps[n] - soff[k];
+        wcnt[k] = pw[n] - woff[k];
+    }
+    if (n == 0) return LBM_OK;
+    int *dl = pl->dlist + M;
+    int64_t *dps = pl->dpref, *dpw = pl->dpref + (M + 1);
+    HIPCHK(hipMemcpyAsync(dl, G.hlist, sizeof(int) * n, hipMemcpyHostToDevice, G.stream));
+    HIPCHK(hipMemcpyAsync(dps, ps, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, G.stream));
+    HIPCHK(hipMemcpyAsync(dpw, pw, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, G.stream));
+    if (ps[n] > 0)
+        hipLaunchKernelGGL(k_mtab, dim3((unsigned)((ps[n] + BLK - 1) / BLK)), dim3(BLK), 0, G.stream, pl->dtab, dps, dl, n);
+    if (pw[n] > 0)
+        hipLaunchKernelGGL(k_mtab, dim3((unsigned)((pw[n] + BLK - 1) / BLK)), dim3(BLK), 0, G.stream, pl->dtab + pl->tab_cap, dpw, dl, n);
+    HIPCHK(hipGetLastError());
+    for (int s = 0; s < chunk; ++s) {
+        bool due = false;
+        for (int i : G.chunk_slots) {
+            const PoolSlot &S = pl->slots[i];
+            const int64_t after = S.steps + s + 1;
+            if (after <= S.max_steps && (after % S.reduce_every == 0 || after == S.max_steps)) due = true;
+        }
+        for (int k = 0; k < NKEY; ++k) {
+            if (!lcnt[k]) continue;
+            const MLaunch m{soff[k], scnt[k], woff[k], wcnt[k], dl + lstart[k], lcnt[k], s};
+            int rc = mlaunch(pl, k, m, false);
+            if (rc) return rc;
+        }
+        if (!due) continue;
+        for (int k = 0; k < NKEY; ++k) {
+            if (!lcnt[k]) continue;
+            const MLaunch m{soff[k], scnt[k], woff[k], wcnt[k], dl + lstart[k], lcnt[k], s};
+            int rc = mlaunch(pl, k, m, true);
+            if (rc) return rc;
+        }
+    }
+    hipLaunchKernelGGL(k_mfinish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, G.stream, pl->dslots, dl, n, chunk);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(G.mirror, pl->dslots, sizeof(SlotDesc) * M, hipMemcpyDeviceToHost, G.stream));
+    HIPCHK(hipEventRecord(G.done, G.stream));
+    G.in_flight = true;
+    return LBM_OK;
+}
+
+int launch_group(lbm_pool *pl, int gi, int chunk) { return gi == 0 ? launch_small(pl, chunk) : launch_large(pl, chunk); }
+
+int wait_group(lbm_pool *pl, int gi)
+{
+    PoolGroup &G = pl->g[gi];
+    if (!G.in_flight) return LBM_OK;
+    HIPCHK(hipEventSynchronize(G.done));
+    harvest(pl, gi);
+    return LBM_OK;
+}
+
+void pool_teardown(lbm_pool *pl)
+{
+    for (auto &G : pl->g) {
+        if (G.stream) (void)hipStreamSynchronize(G.stream);
+        if (G.done) (void)hipEventDestroy(G.done);
+        if (G.mirror) (void)hipHostFree(G.mirror);
+        if (G.hlist) (void)hipHostFree(G.hlist);
+        if (G.hpref) (void)hipHostFree(G.hpref);
+    }
+    for (auto &S : pl->slots)
+        if (S.used && S.h) lbm_destroy(S.h);
+    if (pl->hstage) (void)hipHostFree(pl->hstage);
+    if (pl->g[1].stream) (void)hipStreamDestroy(pl->g[1].stream);
+    delete pl;
 }
 
 }  // namespace
@@ -1587,32 +1990,44 @@ int lbm_pool_create(void *dev_buf, int64_t bytes, int max_slots, void *stream, l
     *out = nullptr;
     if (max_slots < 1 || max_slots > 65536) return fail(LBM_EINVAL, "max_slots must be in [1, 65536]");
     if (!dev_buf || ((uintptr_t)dev_buf & 255u)) return fail(LBM_EINVAL, "pool buffer must be non-NULL and 256-byte aligned");
-    const int64_t desc = align256((int64_t)max_slots * (int64_t)sizeof(SlotDesc));
-    if (bytes < desc + 4096) return fail(LBM_EINVAL, "pool buffer too small");
+    const int64_t M = max_slots;
+    // block tables: at most two blocks per 256 cells, and no cell takes fewer
+    // than 32 bytes of the buffer
+    const int64_t tab_cap = bytes / (32 * 128) + 4 * M;
+    const int64_t desc = align256(M * (int64_t)sizeof(SlotDesc));
+    const int64_t lists = align256(3 * M * (int64_t)sizeof(int));
+    const int64_t prefs = align256(2 * (M + 1) * (int64_t)sizeof(int64_t));
+    const int64_t tabs = align256(2 * tab_cap * (int64_t)sizeof(int2));
+    const int64_t data_off = desc + lists + prefs + tabs;
+    if (bytes < data_off + 4096) return fail(LBM_EINVAL, "pool buffer too small");
     lbm_pool *pl = new (std::nothrow) lbm_pool();
     if (!pl) return fail(LBM_ENOMEM, "host allocation failed");
     pl->base = (char *)dev_buf;
     pl->bytes = bytes;
-    pl->desc_bytes = desc;
     pl->max_slots = max_slots;
-    pl->sA = (hipStream_t)stream;
-    hipError_t e = hipStreamCreateWithFlags(&pl->sB, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        delete pl;
-        return fail(LBM_EHIP, "hipStreamCreate: %s", hipGetErrorString(e));
-    }
     pl->dslots = (SlotDesc *)pl->base;
-    pl->hslots.assign(max_slots, SlotDesc{});
-    for (auto &d : pl->hslots) d.status = SLOT_IDLE;
+    pl->dlist = (int *)(pl->base + desc);
+    pl->dpref = (int64_t *)(pl->base + desc + lists);
+    pl->dtab = (int2 *)(pl->base + desc + lists + prefs);
+    pl->tab_cap = tab_cap;
+    pl->tab_used_step = pl->tab_used_wall = 0;
+    pl->data_off = data_off;
     pl->slots.assign(max_slots, PoolSlot{});
-    pl->freel[desc] = bytes - desc;
-    e = hipMemcpyAsync(pl->dslots, pl->hslots.data(), sizeof(SlotDesc) * max_slots, hipMemcpyHostToDevice, pl->sA);
-    if (e == hipSuccess) e = hipStreamSynchronize(pl->sA);
-    if (e != hipSuccess) {
-        (void)hipStreamDestroy(pl->sB);
-        delete pl;
-        return fail(LBM_EHIP, "pool descriptor upload: %s", hipGetErrorString(e));
+    pl->g[0].stream = (hipStream_t)stream;
+    hipError_t e = hipStreamCreateWithFlags(&pl->g[1].stream, hipStreamNonBlocking);
+    for (int gi = 0; gi < 2 && e == hipSuccess; ++gi) {
+        PoolGroup &G = pl->g[gi];
+        e = hipEventCreateWithFlags(&G.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&G.mirror, sizeof(SlotDesc) * M, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&G.hlist, sizeof(int) * M, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&G.hpref, sizeof(int64_t) * 2 * (M + 1), hipHostMallocDefault);
     }
+    if (e == hipSuccess) e = hipHostMalloc((void **)&pl->hstage, sizeof(SlotDesc) * M, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        pool_teardown(pl);
+        return fail(LBM_EHIP, "pool set-up: %s", hipGetErrorString(e));
+    }
+    pl->freel[data_off] = bytes - data_off;
     *out = pl;
     return LBM_OK;
 }
@@ -1641,13 +2056,24 @@ int lbm_pool_admit(lbm_pool_t *pl, lbm_lattice_t lattice, int nx, int ny, int nz
             break;
         }
     if (idx < 0) return fail(LBM_ENOMEM, "no free slot");
+    const int64_t cells2 = (int64_t)nx * ny;
+    const bool small = lattice == LBM_D2Q9 &&
+                       (cells2 <= SERVE_SMALL_CELLS || (p->flow == LBM_FLOW_CHANNEL && cells2 <= SERVE_SMALL_CHANNEL)) &&
+                       (p->flow == LBM_FLOW_CHANNEL || ny <= SERVE_MAX_NY);
     const int64_t off = pool_alloc(pl, need);
     if (off < 0) return fail(LBM_ENOMEM, "no free block of %lld bytes", (long long)need);
-    const bool small = lattice == LBM_D2Q9 && (int64_t)nx * ny <= SERVE_SMALL_CELLS &&
-                       (p->flow == LBM_FLOW_CHANNEL || ny <= SERVE_MAX_NY);
+    PoolGroup &G = pl->g[small ? 0 : 1];
     lbm *h = nullptr;
-    int rc = lbm_create(lattice, nx, ny, nz, p, pl->base + off, align256(need), small ? pl->sA : pl->sB, &h);
+    int rc = lbm_create(lattice, nx, ny, nz, p, pl->base + off, align256(need), G.stream, &h);
     if (!rc && u0_host) rc = lbm_set_velocity(h, u0_host, 0);
+    int64_t sb = 0, wb = 0;
+    if (!rc && !small) {
+        // blocks of this lattice in the multi-lattice launches (k_mstep, k_mwall)
+        sb = p->flow == LBM_FLOW_PLATE ? (int64_t)ny * ((nx + BLK - 1) / BLK) : (h->kp.ncell + BLK - 1) / BLK;
+        wb = (h->kp.nwall + BLK - 1) / BLK;
+        if (pl->tab_used_step + sb > pl->tab_cap || pl->tab_used_wall + wb > pl->tab_cap || sb > INT32_MAX)
+            rc = fail(LBM_ENOMEM, "pool block table full");
+    }
     if (rc) {
         if (h) lbm_destroy(h);
         pool_free(pl, off, need);
@@ -1661,23 +2087,50 @@ int lbm_pool_admit(lbm_pool_t *pl, lbm_lattice_t lattice, int nx, int ny, int nz
     S.off = off;
     S.bytes = need;
     S.status = SLOT_RUNNING;
-    S.tol = tol;
+    S.key = slot_key(h, small);
     S.max_steps = max_steps;
-    if (small) {
-        SlotDesc &d = pl->hslots[idx];
-        d = SlotDesc{};
-        d.kp = h->kp;
-        d.step = 0;
-        d.snap_step = 0;
-        d.max_steps = max_steps;
-        d.tol = tol;
-        d.status = SLOT_RUNNING;
-        d.reduce_every = h->p.reduce_every > 0 ? h->p.reduce_every : 100;
-        d.variant = variant_of(h->p);
-        HIPCHK(hipMemcpyAsync(pl->dslots + idx, &d, sizeof d, hipMemcpyHostToDevice, pl->sA));
-        HIPCHK(hipStreamSynchronize(pl->sA));
+    S.reduce_every = h->p.reduce_every > 0 ? h->p.reduce_every : 100;
+    S.step_blocks = sb;
+    S.wall_blocks = wb;
+    if (!small) {
+        pl->tab_used_step += sb;
+        pl->tab_used_wall += wb;
     }
+    SlotDesc &d = pl->hstage[idx];
+    d = SlotDesc{};
+    d.kp = h->kp;
+    d.step = 0;
+    d.snap_step = 0;
+    d.stop_step = 0;
+    d.max_steps = max_steps;
+    d.tol = tol;
+    d.status = SLOT_RUNNING;
+    d.reduce_every = (int)S.reduce_every;
+    d.variant = S.key;
+    HIPCHK(hipMemcpyAsync(pl->dslots + idx, &d, sizeof d, hipMemcpyHostToDevice, G.stream));
     *slot = idx;
+    return LBM_OK;
+}
+
+int lbm_pool_pump(lbm_pool_t *pl, int64_t steps, int *in_flight)
+{
+    if (!pl) return fail(LBM_ESTATE, "NULL pool");
+    if (steps < 1 || steps > (1 << 30)) return fail(LBM_EINVAL, "steps must be in [1, 2^30]");
+    for (int gi = 0; gi < 2; ++gi) {
+        PoolGroup &G = pl->g[gi];
+        if (G.in_flight) {
+            const hipError_t e = hipEventQuery(G.done);
+            if (e == hipSuccess)
+                harvest(pl, gi);
+            else if (e != hipErrorNotReady)
+                return fail(LBM_EHIP, "hipEventQuery: %s", hipGetErrorString(e));
+        }
+        if (!G.in_flight) {
+            int rc = launch_group(pl, gi, (int)steps);
+            if (rc) return rc;
+        }
+    }
+    if (in_flight) *in_flight = (pl->g[0].in_flight ? 1 : 0) + (pl->g[1].in_flight ? 1 : 0);
     return LBM_OK;
 }
 
@@ -1685,61 +2138,17 @@ int lbm_pool_step(lbm_pool_t *pl, int64_t steps)
 {
     if (!pl) return fail(LBM_ESTATE, "NULL pool");
     if (steps < 1 || steps > (1 << 30)) return fail(LBM_EINVAL, "steps must be in [1, 2^30]");
-    bool variants[8] = {false};
-    bool any_small = false;
-    for (int i = 0; i < pl->max_slots; ++i) {
-        const PoolSlot &S = pl->slots[i];
-        if (S.used && S.small && S.status == SLOT_RUNNING) {
-            variants[pl->hslots[i].variant & 7] = true;
-            any_small = true;
-        }
+    for (int gi = 0; gi < 2; ++gi) {
+        int rc = wait_group(pl, gi);
+        if (rc) return rc;
     }
-    // small lattices: persistent launches on stream A
-    for (int v = 0; v < 8; ++v)
-        if (variants[v]) {
-            int rc = serve_variant(pl, v, (int)steps);
-            if (rc) return rc;
-        }
-    // large lattices: regular kernels on stream B (overlapping with A)
-    for (int i = 0; i < pl->max_slots; ++i) {
-        PoolSlot &S = pl->slots[i];
-        if (!S.used || S.small || S.status != SLOT_RUNNING) continue;
-        int64_t n = steps;
-        if (S.h->step + n > S.max_steps) n = S.max_steps - S.h->step;
-        if (n > 0) {
-            int rc = lbm_step(S.h, n);
-            if (rc) return rc;
-        }
+    for (int gi = 0; gi < 2; ++gi) {
+        int rc = launch_group(pl, gi, (int)steps);
+        if (rc) return rc;
     }
-    for (int i = 0; i < pl->max_slots; ++i) {
-        PoolSlot &S = pl->slots[i];
-        if (!S.used || S.small || S.status != SLOT_RUNNING) continue;
-        lbm_residual_t r;
-        int rc = lbm_residual(S.h, &r);
-        S.residual = r.l2_du_rel;
-        S.mean_utau = r.mean_u_tau;
-        if (rc == LBM_EDIVERGED)
-            S.status = SLOT_DIVERGED;
-        else if (rc)
-            return rc;
-        else if (r.l2_du_rel < S.tol && r.steps_since_previous > 0)
-            S.status = SLOT_CONVERGED;
-        else if (S.h->step >= S.max_steps)
-            S.status = SLOT_CAPPED;
-    }
-    if (any_small) {
-        HIPCHK(hipMemcpyAsync(pl->hslots.data(), pl->dslots, sizeof(SlotDesc) * pl->max_slots, hipMemcpyDeviceToHost, pl->sA));
-        HIPCHK(hipStreamSynchronize(pl->sA));
-        for (int i = 0; i < pl->max_slots; ++i) {
-            PoolSlot &S = pl->slots[i];
-            if (!S.used || !S.small) continue;
-            const SlotDesc &d = pl->hslots[i];
-            S.status = d.status;
-            S.residual = d.residual;
-            S.mean_utau = d.mean_utau;
-            S.h->step = d.step;
-            S.h->last_reduce_step = -1;
-        }
+    for (int gi = 0; gi < 2; ++gi) {
+        int rc = wait_group(pl, gi);
+        if (rc) return rc;
     }
     return LBM_OK;
 }
@@ -1747,12 +2156,13 @@ int lbm_pool_step(lbm_pool_t *pl, int64_t steps)
 int lbm_pool_poll(lbm_pool_t *pl, int slot, lbm_pool_status_t *out)
 {
     if (!pl) return fail(LBM_ESTATE, "NULL pool");
-    if (slot < 0 || slot >= pl->max_slots || !pl->slots[slot].used) return fail(LBM_EINVAL, "bad slot %d", slot);
+    if (slot < 0 || slot >= pl->max_slots || !pl->slots[slot].used || pl->slots[slot].releasing)
+        return fail(LBM_EINVAL, "bad slot %d", slot);
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     const PoolSlot &S = pl->slots[slot];
     out->status = S.status;
     out->batched = S.small ? 1 : 0;
-    out->steps = S.h->step;
+    out->steps = S.steps;
     out->residual = S.residual;
     out->mean_u_tau = S.mean_utau;
     out->footprint = S.bytes;
@@ -1761,38 +2171,35 @@ int lbm_pool_poll(lbm_pool_t *pl, int slot, lbm_pool_status_t *out)
 
 lbm_t *lbm_pool_lattice(lbm_pool_t *pl, int slot)
 {
-    if (!pl || slot < 0 || slot >= pl->max_slots || !pl->slots[slot].used) return nullptr;
+    if (!pl || slot < 0 || slot >= pl->max_slots || !pl->slots[slot].used || pl->slots[slot].releasing) {
+        fail(LBM_EINVAL, "bad slot %d", slot);
+        return nullptr;
+    }
     return pl->slots[slot].h;
 }
 
 int lbm_pool_release(lbm_pool_t *pl, int slot)
 {
     if (!pl) return fail(LBM_ESTATE, "NULL pool");
-    if (slot < 0 || slot >= pl->max_slots || !pl->slots[slot].used) return fail(LBM_EINVAL, "bad slot %d", slot);
+    if (slot < 0 || slot >= pl->max_slots || !pl->slots[slot].used || pl->slots[slot].releasing)
+        return fail(LBM_EINVAL, "bad slot %d", slot);
     PoolSlot &S = pl->slots[slot];
-    HIPCHK(hipStreamSynchronize(pl->sA));
-    HIPCHK(hipStreamSynchronize(pl->sB));
-    if (S.small) {
-        SlotDesc &d = pl->hslots[slot];
-        d.status = SLOT_IDLE;
-        HIPCHK(hipMemcpyAsync(&pl->dslots[slot].status, &d.status, sizeof d.status, hipMemcpyHostToDevice, pl->sA));
-        HIPCHK(hipStreamSynchronize(pl->sA));
+    PoolGroup &G = pl->g[S.small ? 0 : 1];
+    if (G.in_flight) {
+        // the group's chunk in flight may still touch the slot: free it when
+        // that chunk is harvested
+        S.releasing = true;
+        return LBM_OK;
     }
-    lbm_destroy(S.h);
-    pool_free(pl, S.off, S.bytes);
-    S = PoolSlot{};
+    HIPCHK(hipStreamSynchronize(G.stream));  // the slot's own set-up work
+    finish_release(pl, slot);
     return LBM_OK;
 }
 
 int lbm_pool_destroy(lbm_pool_t *pl)
 {
     if (!pl) return fail(LBM_ESTATE, "NULL pool");
-    (void)hipStreamSynchronize(pl->sA);
-    (void)hipStreamSynchronize(pl->sB);
-    for (auto &S : pl->slots)
-        if (S.used && S.h) lbm_destroy(S.h);
-    (void)hipStreamDestroy(pl->sB);
-    delete pl;
+    pool_teardown(pl);
     return LBM_OK;
 }
 

@@ -119,6 +119,7 @@ def lib() -> ctypes.CDLL:
                                           P, vp, ctypes.c_double, i64,
                                           ctypes.POINTER(ctypes.c_int)]),
         "lbm_pool_step": (ctypes.c_int, [vp, i64]),
+        "lbm_pool_pump": (ctypes.c_int, [vp, i64, ctypes.POINTER(ctypes.c_int)]),
         "lbm_pool_poll": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(lbm_pool_status_t)]),
         "lbm_pool_lattice": (vp, [vp, ctypes.c_int]),
         "lbm_pool_release": (ctypes.c_int, [vp, ctypes.c_int]),
@@ -336,6 +337,13 @@ class Pool:
 
     def lbm_pool_step(self, steps: int):
         _check(lib().lbm_pool_step(self.h, int(steps)))
+
+    def lbm_pool_pump(self, steps: int) -> int:
+        """Non-blocking: harvest finished chunks, launch the next ones; returns
+        the number of groups (0-2) with work on the device."""
+        n = ctypes.c_int(0)
+        _check(lib().lbm_pool_pump(self.h, int(steps), ctypes.byref(n)))
+        return n.value
 
     def lbm_pool_poll(self, slot: int) -> dict:
         st = lbm_pool_status_t()

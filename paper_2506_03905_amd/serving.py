@@ -2,8 +2,10 @@
 
 Continuous batching over the C ABI's pool (lbm_pool_*): requests are
 admitted in arrival order as soon as a slot and a block of their footprint
-are free; all resident lattices advance together (small ones in one
-persistent launch, large ones on a second stream); a lattice leaves the pool
+are free; all resident lattices advance together in two groups that run
+concurrently (small lattices in persistent launches, the others in
+multi-lattice launches on a second stream), each group relaunched as soon as
+its previous chunk of steps ends (lbm_pool_pump); a lattice leaves the pool
 when its residual ||u^n - u^(n-K)|| / (K ||u^n||) falls below the tolerance,
 when it diverges or when it reaches the step cap.  The sequential baseline
 runs the same requests one at a time with the plain per-lattice path.
@@ -66,7 +68,7 @@ def _summary(results: dict, makespan: float) -> dict:
     }
 
 
-def run_batched(requests: list, pool_bytes: int, chunk: int = 500, tol: float = 1e-8,
+def run_batched(requests: list, pool_bytes: int, chunk: int = 200, tol: float = 1e-8,
                 max_steps: int = 20000, max_slots: int = 1024, keep_fields: set = frozenset(),
                 device="cuda:0", log=None) -> tuple:
     """Continuous batching in one pool.  Returns (results by id, summary)."""
@@ -87,8 +89,9 @@ def run_batched(requests: list, pool_bytes: int, chunk: int = 500, tol: float = 
         if not active:
             time.sleep(max(0.0, min(reqs[i]["t_arrival"] - now, 0.05)))
             continue
-        pool.lbm_pool_step(chunk)
+        busy = pool.lbm_pool_pump(chunk)
         now = time.perf_counter() - t0
+        finished = 0
         for slot in list(active):
             st = pool.lbm_pool_poll(slot)
             if st["status"] == L.LBM_SLOT_RUNNING:
@@ -104,9 +107,12 @@ def run_batched(requests: list, pool_bytes: int, chunk: int = 500, tol: float = 
                 res["utau"] = v.lbm_wall()["utau"]
             results[req["id"]] = res
             pool.lbm_pool_release(slot)
+            finished += 1
             if log:
                 log(f"done {req['id']} {req['kind']} {req['nx']}x{req['ny']} steps={st['steps']} "
                     f"status={st['status']} latency={res['latency']:.3f}s")
+        if not finished and busy:
+            time.sleep(2e-4)
     makespan = time.perf_counter() - t0
     pool.close()
     return results, _summary(results, makespan)

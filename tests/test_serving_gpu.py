@@ -36,8 +36,8 @@ def _oracle_for(req, steps):
 
 @pytest.mark.parametrize("req", [_req(0, "channel", 64, 2000.0, "slip_bb"),
                                  _req(1, "channel", 48, 900.0, "hrfd"),
-                                 _req(2, "plate", 32, 800.0, "slip_bb"),
-                                 _req(3, "plate", 32, 3000.0, "hrfd")])
+                                 _req(2, "plate", 16, 800.0, "slip_bb"),
+                                 _req(3, "plate", 16, 3000.0, "hrfd")])
 def test_batched_fp64_matches_oracle(req):
     """The persistent small-lattice kernel (FP64 storage) against the oracle."""
     _gpu()
@@ -57,11 +57,93 @@ def test_batched_fp64_matches_oracle(req):
     pool.close()
 
 
+@pytest.mark.parametrize("req", [_req(0, "plate", 40, 800.0, "slip_bb"),
+                                 _req(1, "plate", 48, 3000.0, "hrfd"),
+                                 _req(2, "plate", 40, 1500.0, "cai_degrigny")])
+def test_multi_lattice_fp64_matches_oracle(req):
+    """The multi-lattice launches of the large-lattice group (FP64 storage)
+    against the oracle, through a cap that is not a multiple of the chunk."""
+    _gpu()
+    lat, nx, ny, nz, p, _ = serving.request_lattice(req)
+    p.precision = L.LBM_F64
+    pool = L.Pool(256 << 20, max_slots=8)
+    slot = pool.lbm_pool_admit(lat, nx, ny, nz, p, None, 0.0, 250)
+    pool.lbm_pool_step(100)
+    pool.lbm_pool_step(100)
+    pool.lbm_pool_step(100)
+    st = pool.lbm_pool_poll(slot)
+    assert not st["batched"] and st["steps"] == 250 and st["status"] == L.LBM_SLOT_CAPPED
+    v = pool.lbm_pool_lattice(slot)
+    _, ug, _ = v.lbm_moments()
+    o = _oracle_for(req, 250)
+    assert np.abs(ug - o.u()).max() / np.abs(o.u()).max() < 1e-10
+    ut = v.lbm_wall()["utau"]
+    assert np.abs(ut - o.wall()["utau"]).max() / o.wall()["utau"].max() < 1e-10
+    pool.close()
+
+
+def test_multi_lattice_d3q19_fp64_matches_oracle():
+    """A D3Q19 channel in the pool (large-lattice group) against the oracle."""
+    _gpu()
+    lat = units.channel(5000.0, 6)
+    nx, ny, nz = 5, 12, 4
+    u0 = inputs.channel_velocity(0, 3, nz, ny, nx, lat["u_bulk"], 1e-3)
+    p = L.lbm_params_default(precision=L.LBM_F64, scheme=L.LBM_WALL_SLIP_BB, nu=lat["nu"],
+                             force=(lat["force"] * 10, 0, 0), reduce_every=10)
+    pool = L.Pool(64 << 20, max_slots=4)
+    slot = pool.lbm_pool_admit(L.LBM_D3Q19, nx, ny, nz, p, u0, 0.0, 25)
+    pool.lbm_pool_step(40)
+    st = pool.lbm_pool_poll(slot)
+    assert not st["batched"] and st["steps"] == 25
+    _, ug, _ = pool.lbm_pool_lattice(slot).lbm_moments()
+    op = O.params(q=19, nx=nx, ny=ny, nz=nz, nu=lat["nu"], force=(lat["force"] * 10, 0, 0),
+                  scheme=O.BB_SLIP)
+    o = O.Oracle(op, u0)
+    o.step(25)
+    assert np.abs(ug - o.u()).max() / np.abs(o.u()).max() < 1e-11
+    pool.close()
+
+
+def test_pump_staggered_admission_equals_alone():
+    """Continuous batching: requests admitted while others are on the device
+    (staggered through lbm_pool_pump) end with the same fields, steps and
+    status as each request run alone."""
+    _gpu()
+    reqs = [_req(0, "channel", 64, 2000.0, "slip_bb"), _req(1, "plate", 64, 1200.0, "hrfd"),
+            _req(2, "channel", 200, 6000.0, "hrfd"), _req(3, "plate", 24, 900.0, "slip_bb")]
+    cap = 700
+
+    def run(subset, stagger):
+        pool = L.Pool(1 << 30, max_slots=16)
+        pending = list(subset)
+        slots, done = {}, {}
+        while pending or len(done) < len(slots):
+            if pending:
+                r = pending.pop(0)
+                lat, nx, ny, nz, p, _ = serving.request_lattice(r)
+                slots[r["id"]] = pool.lbm_pool_admit(lat, nx, ny, nz, p, None, 0.0, cap)
+            for _ in range(stagger if pending else 1):
+                pool.lbm_pool_pump(100)
+            for i, sl in slots.items():
+                st = pool.lbm_pool_poll(sl)
+                if i not in done and st["status"] != L.LBM_SLOT_RUNNING:
+                    done[i] = (st["steps"], st["status"], pool.lbm_pool_lattice(sl).lbm_moments()[1])
+        pool.close()
+        return done
+
+    mixed = run(reqs, 3)
+    for r in reqs:
+        alone = run([r], 1)[r["id"]]
+        got = mixed[r["id"]]
+        assert got[0] == alone[0] == cap and got[1] == alone[1] == L.LBM_SLOT_CAPPED
+        assert np.array_equal(got[2], alone[2]), r
+
+
 def test_alone_equals_mixed_bitwise():
     """Each request's fields after the same number of steps are bitwise equal
     whether it runs alone or together with others (small and large tiers)."""
     _gpu()
-    reqs = [_req(0, "channel", 64, 2000.0, "slip_bb"), _req(1, "plate", 40, 1200.0, "hrfd"),
+    reqs = [_req(0, "channel", 64, 2000.0, "slip_bb"), _req(1, "plate", 16, 1200.0, "hrfd"),
             _req(2, "plate", 320, 5000.0, "slip_bb"), _req(3, "channel", 128, 9000.0, "hrfd")]
     steps = 400
 
