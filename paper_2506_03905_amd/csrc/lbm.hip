@@ -39,6 +39,9 @@ using namespace lbmd;
 namespace {
 
 constexpr int BLK = 256;
+#ifndef LBM_XSTAGE
+#define LBM_XSTAGE 1
+#endif
 #ifndef LBM_ROWMAP
 #define LBM_ROWMAP 1
 #endif
@@ -117,6 +120,26 @@ template <int Q> __device__ __forceinline__ int64_t poff(const Cell &C, int ccx,
            (int64_t)Q * ((int64_t)ccy * C.sy + (ccz > 0 ? C.ozp : (ccz < 0 ? C.ozm : 0)));
 }
 
+// Staged odd-step pushes (XS): on the channel's row mapping a block covers BLK
+// consecutive columns of one row; the x-shifted pushes that land inside the
+// block are staged in LDS at their destination column and written after one
+// barrier as whole aligned runs.  A push shifted by one column straight to
+// HBM leaves every cache line of its run written in two parts by two waves,
+// which costs HBM write efficiency; staged, only the block's two edge
+// columns are written alone.  Directions with c_x != 0 own one LDS row each.
+template <int Q> __host__ __device__ constexpr int nxdirs()
+{
+    int n = 0;
+    for (int i = 0; i < Q; ++i) n += cx<Q>(i) != 0;
+    return n;
+}
+template <int Q> __host__ __device__ constexpr int xslot(int i)
+{
+    int n = 0;
+    for (int k = 0; k < i; ++k) n += cx<Q>(k) != 0;
+    return n;
+}
+
 // ---------------------------------------------------------------------------
 // gather: the incoming populations of one cell (deviations f - w rho0) with
 // the wall links (eq. 31) and symmetry planes resolved; the open-boundary
@@ -149,27 +172,23 @@ __device__ __forceinline__ void gather(const KP &P, const Cell &C, T *f)
         const bool xopen = PLATE && ((ccx > 0 && x == 0) || (ccx < 0 && x == nx - 1));
         const bool ycross = (ccy > 0 && bottom) || (ccy < 0 && top);
         const bool wall = ycross && (top ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, -ccx));
-        T v = 0;
-        if (active && !xopen) {
-            // the slot holds population i (interior), opp(i) (wall) or mir(i) (symmetry)
-            if (!ODD)
-                v = SS::ld(ld_pop(&A[pb + i * nx]));
-            else if (!ycross)
-                v = SS::ld(ld_pop(&A[pb + io * nx + poff<Q>(C, -ccx, -ccy, -ccz)]));
-            else if (wall)
-                v = SS::ld(ld_pop(&A[pb + i * nx]));
-            else
-                v = SS::ld(ld_pop(&A[pb + im * nx + poff<Q>(C, -ccx, 0, -ccz)]));
-            if (shifted)
-                v += !ycross ? shift_off<Q, T>(i, r0, Us)
-                             : (wall ? shift_off<Q, T>(opp<Q>(i), r0, Us) : shift_off<Q, T>(mir<Q>(i), r0, Us));
-            // eq. 31: f_i = f*_opp(i) + 2 w_i rho_w (c_i . u_w) / cs2
-            if (!HRFD && wall && wi >= 0)
-                v += (T)(6.0 * wgt<Q>(i)) * rho_w * ((T)ccx * uwv[0] + (T)ccy * uwv[1] + (T)ccz * uwv[2]);
-        }
-        f[i] = v;
+        // the slot holds population i (interior), opp(i) (wall) or mir(i)
+        // (symmetry); the index is selected, not branched on, so that every
+        // load is issued unconditionally (an open-boundary unknown reads a
+        // slot of its own row and is discarded)
+        int64_t idx = pb + i * nx;
+        if (ODD)
+            idx = !ycross ? pb + io * nx + poff<Q>(C, -ccx, -ccy, -ccz)
+                          : (wall ? pb + i * nx : pb + im * nx + poff<Q>(C, -ccx, 0, -ccz));
+        T v = SS::ld(ld_pop(&A[idx]));
+        if (shifted)
+            v += !ycross ? shift_off<Q, T>(i, r0, Us)
+                         : (wall ? shift_off<Q, T>(opp<Q>(i), r0, Us) : shift_off<Q, T>(mir<Q>(i), r0, Us));
+        // eq. 31: f_i = f*_opp(i) + 2 w_i rho_w (c_i . u_w) / cs2
+        if (!HRFD && wall && wi >= 0)
+            v += (T)(6.0 * wgt<Q>(i)) * rho_w * ((T)ccx * uwv[0] + (T)ccy * uwv[1] + (T)ccz * uwv[2]);
+        f[i] = (active && !xopen) ? v : (T)0;
     });
-
 }
 
 // Zou-He inlet (D2Q9, west face, u = (U, 0)): the known weights sum to 1 in
@@ -189,8 +208,8 @@ template <typename T> __device__ __forceinline__ void zou_he(const KP &P, T *f)
 // velocity, wall density and the Spalart-Allmaras update of one cell.
 // rd: ping-pong index of u^{n-1} / nu_tilde^n; results go to rd ^ 1.
 // ---------------------------------------------------------------------------
-template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC>
-__device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f)
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false>
+__device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f, S *lds = nullptr)
 {
     constexpr int D = Lat<Q>::D;
     using SS = Stor<S>;
@@ -302,23 +321,27 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f)
         constexpr int ccxi = cx<Q>(i), ccyi = cy<Q>(i), cczi = cz<Q>(i);
         constexpr int io = opp<Q>(i), im = mir<Q>(i);
         const T fp = shifted ? f[i] - shift_off<Q, T>(i, r0, Us) : f[i];
-        if (!ODD) {
-            st_pop(&A[pb + io * nx], SS::st(fp));
-        } else {
+        // even step: own slot opp(i); odd step: the neighbour's slot i, or the
+        // own free slot opp(i) for a population leaving through a wall or an
+        // open boundary, or the mirrored destination across a symmetry plane
+        // (index selected, store unconditional)
+        int64_t idx = pb + io * nx;
+        if (ODD) {
             const bool xopen = PLATE && ((ccxi > 0 && x == nx - 1) || (ccxi < 0 && x == 0));
             const bool ycross = (ccyi < 0 && bottom) || (ccyi > 0 && top);
-            if (xopen) {
-                st_pop(&A[pb + io * nx], SS::st(fp));
-            } else if (!ycross) {
-                st_pop(&A[pb + i * nx + poff<Q>(C, ccxi, ccyi, cczi)], SS::st(fp));
-            } else {
-                const bool wall = top ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, ccxi);
-                if (wall)
-                    st_pop(&A[pb + io * nx], SS::st(fp));
-                else
-                    st_pop(&A[pb + im * nx + poff<Q>(C, ccxi, 0, cczi)], SS::st(fp));
+            const bool wall = top ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, ccxi);
+            if (!xopen)
+                idx = !ycross ? pb + i * nx + poff<Q>(C, ccxi, ccyi, cczi)
+                              : (wall ? pb + io * nx : pb + im * nx + poff<Q>(C, ccxi, 0, cczi));
+            if constexpr (XS && ccxi != 0) {
+                const int xd = x + ccxi, t = (int)threadIdx.x + ccxi;
+                if (!ycross && xd >= 0 && xd < nx && t >= 0 && t < BLK) {
+                    lds[xslot<Q>(i) * BLK + t] = SS::st(fp);
+                    return;
+                }
             }
         }
+        st_pop(&A[idx], SS::st(fp));
     });
     u_wr[cell] = ux;
     u_wr[N + cell] = uy;
@@ -326,6 +349,7 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f)
     if (wi >= 0) P.wrho[wi] = (double)rho;
 
     // ---- Spalart-Allmaras update from nu_tilde^n and u^{n-1} -------------------
+    auto sa_update = [&]() {
     if (!P.sa_on) return;
     const bool dirichlet = (wi >= 0) || (PLATE && x == 0);
     if (dirichlet) {
@@ -360,6 +384,8 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f)
     const T d = wall_dist<T>(P, x, y);
     const T rhs = sa_rhs<D, T>(P, nt0, ntm, ntp, u0, g, d);
     nt_wr[cell] = clamp0(nt0 + rhs);
+    };
+    sa_update();
 }
 
 // ---------------------------------------------------------------------------
@@ -367,12 +393,34 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f)
 // a BLK-thread block.  Plate blocks must be aligned to the right end of a row
 // (columns nx-2 and nx-1 in one block) for the outlet exchange through LDS.
 // ---------------------------------------------------------------------------
-template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC>
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false>
 __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, int z, bool active)
 {
     const int nx = P.nx;
     const int tid = threadIdx.x;
     const Cell C = make_cell<Q, PLATE>(P, x, y, z, active);
+    if constexpr (XS) {
+        // a block covers columns [x - tid, x - tid + BLK) of one row
+        __shared__ S lds[nxdirs<Q>() * BLK];
+        T f[Q];
+        if (active) {
+            gather<Q, S, T, ODD, PLATE, HRFD>(P, C, f);
+            finish<Q, S, T, ODD, PLATE, HRFD, CMC, true>(P, C, rd, f, lds);
+        }
+        __syncthreads();
+        S *__restrict__ A = (S *)P.pops;
+        sfor<Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int ccx = cx<Q>(i), ccy = cy<Q>(i), ccz = cz<Q>(i);
+            if constexpr (ccx != 0) {
+                const bool ycross = (ccy < 0 && C.bottom) || (ccy > 0 && C.top);
+                const int src = tid - ccx;  // thread that staged column x
+                if (active && !ycross && src >= 0 && src < BLK && x - ccx >= 0 && x - ccx < nx)
+                    st_pop(&A[C.pb + i * nx + poff<Q>(C, 0, ccy, ccz)], lds[xslot<Q>(i) * BLK + tid]);
+            }
+        });
+        return;
+    }
     T f[Q];
     if (active) gather<Q, S, T, ODD, PLATE, HRFD>(P, C, f);
     if (PLATE) {
@@ -426,6 +474,10 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         z = (int)(r / rows);
         x = (int)(seg * BLK) + tid;
         active = x < nx;
+        if constexpr (ODD && !PLATE && LBM_XSTAGE) {
+            cell_update<Q, S, T, ODD, PLATE, HRFD, CMC, true>(P, rd, x, y, z, active);
+            return;
+        }
     } else if (!PLATE) {
         const int64_t cell = xcd_block(blockIdx.x, gridDim.x) * BLK + tid;
         active = cell < N;

@@ -109,9 +109,15 @@ template <int Q, typename T> __device__ __forceinline__ T shift_off(int i, T rho
 #ifndef LBM_NT_POPS
 #define LBM_NT_POPS 1
 #endif
+#ifndef LBM_NT_LD
+#define LBM_NT_LD LBM_NT_POPS
+#endif
+#ifndef LBM_NT_ST
+#define LBM_NT_ST LBM_NT_POPS
+#endif
 template <typename S> __device__ __forceinline__ S ld_pop(const S *p)
 {
-#if LBM_NT_POPS
+#if LBM_NT_LD
     if constexpr (std::is_same<S, bf16s>::value) {
         bf16s r;
         r.b = __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(p));
@@ -125,7 +131,7 @@ template <typename S> __device__ __forceinline__ S ld_pop(const S *p)
 }
 template <typename S> __device__ __forceinline__ void st_pop(S *p, S v)
 {
-#if LBM_NT_POPS
+#if LBM_NT_ST
     if constexpr (std::is_same<S, bf16s>::value)
         __builtin_nontemporal_store(v.b, reinterpret_cast<uint16_t *>(p));
     else

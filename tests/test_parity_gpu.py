@@ -116,6 +116,35 @@ def test_d3q19_channel_slip_bb_f64(steps):
     _compare_f64(o, g)
 
 
+@pytest.mark.parametrize("collision", [O.BGK, O.CM])
+@pytest.mark.parametrize("steps", [1, 2, 25])
+def test_d3q19_row_block_odd_step_f64(steps, collision):
+    """Channel rows that fit one block (nx % 64 == 0, ny % 8 == 0): the odd
+    steps run one block per row with the x-shifted populations exchanged
+    through LDS."""
+    lat = units.channel(5000.0, 8)
+    nx, ny, nz = 128, 16, 4
+    u0 = _channel_u0(19, nx, ny, nz, lat["u_bulk"])
+    o, g = _pair(19, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"] * 10, 0, 0), collision=collision)
+    o.step(steps)
+    g.lbm_step(steps)
+    _compare_f64(o, g)
+    assert np.abs(g.lbm_populations() - o.f()).max() < 1e-13
+
+
+@pytest.mark.parametrize("scheme", [O.BB_SLIP, O.HRFD, O.CAI_DEGRIGNY])
+def test_d2q9_row_block_odd_step_f64(scheme):
+    lat = units.channel(4200.0, 8)
+    nx, ny = 192, 16
+    u0 = _channel_u0(9, nx, ny, 1, lat["u_bulk"])
+    o, g = _pair(9, nx, ny, 1, scheme=scheme, u0=u0, nu=lat["nu"], force=(lat["force"], 0, 0),
+                 collision=O.CM)
+    o.step(31)
+    g.lbm_step(31)
+    _compare_f64(o, g)
+
+
 @pytest.mark.parametrize("scheme", [O.BB_SLIP, O.HRFD, O.CAI_DEGRIGNY])
 @pytest.mark.parametrize("steps", [1, 2, 60])
 def test_d2q9_plate_f64(scheme, steps):
