@@ -329,8 +329,12 @@ def _invariant_channel(q, nx, ny, nz, precision, steps, collision=O.BGK, shift=0
     err = np.linalg.norm(col - uo) / np.linalg.norm(uo)
     ut_g, ut_o = g.lbm_wall()["utau"], o.wall()["utau"]
     ut_err = abs(ut_g.mean() - ut_o.mean()) / ut_o.mean()
+    # per wall cell: bottom cells first, then top (the oracle column has one each)
+    ref = np.repeat(ut_o, ut_g.size // 2)
+    ut_l2 = np.linalg.norm(ut_g - ref) / np.linalg.norm(ref)
+    cf_l2 = np.linalg.norm(ut_g ** 2 - ref ** 2) / np.linalg.norm(ref ** 2)  # Cf = 2 (u_tau / U)^2
     _report(f"{nx}x{ny}x{nz} {precision} shift={shift} steps={steps}",
-            {"u_rel_l2": err, "u_tau_rel": ut_err})
+            {"u_rel_l2": err, "u_tau_rel": ut_err, "u_tau_rel_l2": ut_l2, "cf_rel_l2": cf_l2})
     return err, ut_err
 
 
@@ -362,6 +366,82 @@ def test_config4_full_size_precision(precision, shift, tol_u, tol_ut):
     oracle column (relative L2 of u, relative error of the mean u_tau)."""
     err, ut_err = _invariant_channel(19, 768, 384, 384, precision, 100, shift=shift)
     assert err < tol_u and ut_err < tol_ut, (err, ut_err)
+
+
+_SUB = {}
+
+
+def _subsample_oracle(steps):
+    """The oracle on the 96 x 48 x 48 subsample of the precision workload
+    (Re_tau 5000, 24 cells per half channel, seeded 1e-3 perturbation)."""
+    if steps not in _SUB:
+        lat = units.channel(5000.0, 24, 0.05)
+        nx, ny, nz = 96, 48, 48
+        u0 = inputs.channel_velocity(0, 3, nz, ny, nx, lat["u_bulk"], 1e-3)
+        op = O.params(q=19, nx=nx, ny=ny, nz=nz, nu=lat["nu"], force=(lat["force"], 0, 0),
+                      scheme=O.BB_SLIP)
+        o = O.Oracle(op, u0)
+        o.step(steps)
+        _SUB[steps] = (lat, u0, o.u(), o.wall()["utau"])
+    return _SUB[steps]
+
+
+@pytest.mark.parametrize("precision,shift,tol_u,tol_ut", [
+    ("f32", 0.0, 1e-4, 1e-4),
+    ("f16", 0.0, 1e-3, 2e-3),
+    ("f16", 1.0, 1e-3, 1e-3),
+    ("bf16", 0.0, 2e-2, 5e-2),
+    ("bf16", 1.0, 1e-2, 2e-2),
+])
+def test_config4_subsample_precision(precision, shift, tol_u, tol_ut):
+    """96 x 48 x 48 D3Q19 with a seeded perturbation (a full 3-D field, no
+    symmetry used) against the FP64 oracle: relative L2 of u, of u_tau per
+    wall cell and of Cf = 2 (u_tau / U_b)^2."""
+    _torch_gpu()
+    steps = 60
+    lat, u0, uo, ut_o = _subsample_oracle(steps)
+    gp = L.lbm_params_default(precision=L.PRECISION[precision], scheme=L.LBM_WALL_SLIP_BB,
+                              nu=lat["nu"], force=(lat["force"], 0, 0), reduce_every=0,
+                              store_shift_u=shift * lat["u_bulk"], u_ref=lat["u_bulk"])
+    g = L.Lattice(L.LBM_D3Q19, 96, 48, 48, gp)
+    g.lbm_set_velocity(u0)
+    g.lbm_step(steps)
+    _, ug, _ = g.lbm_moments()
+    w = g.lbm_wall()
+    err = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    ut_l2 = np.linalg.norm(w["utau"] - ut_o) / np.linalg.norm(ut_o)
+    cf_o = 2.0 * (ut_o / lat["u_bulk"]) ** 2
+    cf_l2 = np.linalg.norm(w["cf"] - cf_o) / np.linalg.norm(cf_o)
+    _report(f"96x48x48 perturbed {precision} shift={shift} steps={steps}",
+            {"u_rel_l2": err, "u_tau_rel_l2": ut_l2, "cf_rel_l2": cf_l2})
+    assert err < tol_u and ut_l2 < tol_ut and cf_l2 < 2.5 * tol_ut, (err, ut_l2, cf_l2)
+
+
+@pytest.mark.parametrize("scheme", [O.BB_SLIP, O.HRFD])
+def test_config2_plate_cf_profile_f32(scheme):
+    """Flat plate at the plate workload's viscosity (tau - 1/2 = 6e-5, U = 0.1,
+    CM collision) on a 256 x 32 lattice, FP32 storage and arithmetic against
+    the FP64 oracle after 2000 steps: relative L2 of u and of the skin
+    friction profile Cf(x) = 2 (u_tau / U)^2, and the integrated error of the
+    plate's second half, int |Cf - Cf_ref| dx / int Cf_ref dx (trapezoid)."""
+    nx, ny, U, ps = 256, 32, 0.1, 8
+    nu = U * 992 / 5e6
+    u0 = inputs.channel_velocity(0, 2, 1, ny, nx, U, 0.0)
+    o, g = _pair(9, nx, ny, 1, scheme=scheme, u0=u0, nu=nu, flow=O.PLATE, plate_start=ps,
+                 u_inlet=U, collision=O.CM, precision="f32")
+    o.step(2000)
+    g.lbm_step(2000)
+    _, ug, _ = g.lbm_moments()
+    uo = o.u()
+    err_u = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    cf_g = 2 * (g.lbm_wall()["utau"] / U) ** 2
+    cf_o = 2 * (o.wall()["utau"] / U) ** 2
+    err_cf = np.linalg.norm(cf_g - cf_o) / np.linalg.norm(cf_o)
+    half = (nx - ps) // 2
+    eps = np.trapezoid(np.abs(cf_g - cf_o)[half:]) / np.trapezoid(cf_o[half:])
+    _report(f"plate 256x32 f32 {'hrfd' if scheme == O.HRFD else 'slip_bb'} steps=2000",
+            {"u_rel_l2": err_u, "cf_rel_l2": err_cf, "cf_integrated": eps})
+    assert err_u < 1e-4 and err_cf < 1e-4 and eps < 1e-4, (err_u, err_cf, eps)
 
 
 @pytest.mark.parametrize("scheme", [O.BB_SLIP, O.HRFD])
