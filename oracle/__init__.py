@@ -25,6 +25,7 @@ CHANNEL, PLATE = 0, 1
 BB_FIXED, BB_SLIP, HRFD, CAI_DEGRIGNY = 0, 1, 2, 3
 REICHARDT, SA_LAW = 0, 1
 BGK, CM = 0, 1
+IBB_HALFWAY, IBB_BOUZIDI, IBB_YU = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -50,14 +51,16 @@ class Params(ctypes.Structure):
         ("kappa", ctypes.c_double), ("B", ctypes.c_double), ("beta", ctypes.c_double),
         ("cb1", ctypes.c_double), ("cb2", ctypes.c_double), ("sigma", ctypes.c_double),
         ("cw2", ctypes.c_double), ("cw3", ctypes.c_double), ("cv1", ctypes.c_double),
-        ("rlim", ctypes.c_double),
+        ("rlim", ctypes.c_double), ("bb_interp", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("wall_dist", ctypes.c_double),
     ]
 
 
 def params(q=9, nx=4, ny=64, nz=1, flow=CHANNEL, scheme=BB_SLIP, law=REICHARDT, sa_on=1,
            plate_start=0, nu=1e-3, rho0=1.0, force=(0.0, 0.0, 0.0), u_inlet=0.0,
            wall_u_bottom=(0.0, 0.0, 0.0), wall_u_top=(0.0, 0.0, 0.0), nut_init_ratio=3.0,
-           kappa=0.41, B=5.2, beta=0.28, collision=BGK) -> Params:
+           kappa=0.41, B=5.2, beta=0.28, collision=BGK, bb_interp=0,
+           wall_dist=0.5) -> Params:
     """Parameters with the SA constants listed after eq. 14."""
     p = Params()
     p.q, p.nx, p.ny, p.nz = q, nx, ny, nz
@@ -70,6 +73,7 @@ def params(q=9, nx=4, ny=64, nz=1, flow=CHANNEL, scheme=BB_SLIP, law=REICHARDT, 
     p.nut_init_ratio, p.kappa, p.B, p.beta = nut_init_ratio, kappa, B, beta
     p.cb1, p.cb2, p.sigma = 0.1355, 0.622, 2.0 / 3.0
     p.cw2, p.cw3, p.cv1, p.rlim = 0.3, 2.0, 7.1, 10.0
+    p.bb_interp, p.wall_dist = bb_interp, wall_dist
     return p
 
 

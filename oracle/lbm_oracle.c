@@ -404,12 +404,16 @@ struct orc {
 static int64_t cidx(const orc *o, int x, int y, int z) { return x + (int64_t)o->p.nx * (y + (int64_t)o->p.ny * z); }
 static int wrapi(int a, int n) { return ((a % n) + n) % n; }
 
-/* wall distance (Sec. 2.2: distance to the closest wall), cell centres */
+/* wall distance (Sec. 2.2: distance to the closest wall).  Node y lies
+ * y + d_w above the bottom wall (d_w = wall_dist, 1/2 for halfway walls); the
+ * channel's top wall lies d_w above node ny - 1; the plate's leading-edge
+ * point is at x = plate_start on the wall plane (node x at x + 1/2). */
 static double wall_distance(const orc *o, int x, int y)
 {
-    double yc = y + 0.5;
+    const double dw = o->p.wall_dist;
+    double yc = y + dw;
     if (o->p.flow == ORC_CHANNEL) {
-        double yt = o->p.ny - yc;
+        double yt = (o->p.ny - 1 - y) + dw;
         return yc < yt ? yc : yt;
     }
     double xc = x + 0.5, dx = o->p.plate_start - xc;
@@ -431,7 +435,7 @@ static int sa_dirichlet(const orc *o, int64_t cell, int x)
 static void wall_function(orc *o, double *nt_out)
 {
     const orc_params *p = &o->p;
-    const double yB = 0.5, yF = 1.5;
+    const double yB = p->wall_dist, yF = 1.0 + p->wall_dist; /* Sec. 3.1: B and F */
     for (int64_t w = 0; w < o->nwall; ++w) {
         double n[3] = {0.0, (double)o->wside[w], 0.0};
         double uF[3], uB[3];
@@ -475,6 +479,10 @@ orc *orc_create(const orc_params *p, const double *u0)
     if (p->nx < 1 || p->ny < 4 || p->nz < 1) return NULL;
     if (p->flow == ORC_PLATE && (p->q != 9 || p->nx < 4)) return NULL;
     if ((p->scheme == ORC_HRFD || p->scheme == ORC_CAI_DEGRIGNY) && p->q != 9) return NULL;
+    /* interpolated links are bounce-back rules; any other wall sits halfway */
+    if (p->bb_interp < ORC_IBB_HALFWAY || p->bb_interp > ORC_IBB_YU) return NULL;
+    if (p->bb_interp != ORC_IBB_HALFWAY && p->scheme != ORC_BB_FIXED && p->scheme != ORC_BB_SLIP) return NULL;
+    if (p->bb_interp == ORC_IBB_HALFWAY ? p->wall_dist != 0.5 : !(p->wall_dist > 0.0 && p->wall_dist <= 1.0)) return NULL;
     orc *o = (orc *)calloc(1, sizeof(orc));
     o->p = *p;
     o->D = p->q == 9 ? 2 : 3;
@@ -552,13 +560,65 @@ void orc_destroy(orc *o)
 /* Does a population that reaches cell (x, y) through the wall-normal face
  * side (-1 bottom, +1 top) with x-velocity cx reflect off a wall (1) or a
  * symmetry plane (0)?  Channel: walls.  Plate: the top is a symmetry plane;
- * at the bottom the crossing point X = x + 1/2 - cx/2 decides: on the plate
- * (X >= plate_start, the leading-edge point included) it is a wall. */
+ * at the bottom the point X = x + 1/2 - d_w cx where the outgoing link meets
+ * the wall plane decides: on the plate (X >= plate_start, the leading-edge
+ * point included) it is a wall.  For d_w = 1/2: 2x + 1 - cx >= 2 plate_start. */
 static int crossing_is_wall(const orc *o, int x, int side, int cx)
 {
     if (o->p.flow == ORC_CHANNEL) return 1;
     if (side > 0) return 0;
-    return 2 * x + 1 - cx >= 2 * o->p.plate_start;
+    return x + 0.5 - o->p.wall_dist * cx >= (double)o->p.plate_start;
+}
+
+/* Interpolated bounce-back at the wall cells (eq. 36, eq. 37) with the wall
+ * at q = wall_dist from B along every wall-crossing link (a flat wall).  For
+ * the link k into the wall and its reflection r = opp(k): f*_k(B) leaves B
+ * towards the wall, f_k(B, t+1) = f*_k(F) arrived at B from F = B - c_k, and
+ * f*_r(B) is B's own population leaving the wall one step earlier, which is
+ * f_r(F, t+1).  rho_w = rho_B; the moving-wall term is eq. 31's.
+ * Plate: the outlet column is treated after the outlet copy (outlet = 1),
+ * the other columns before it (outlet = 0), so that the copy carries the
+ * interpolated values of column nx - 2; a reflection whose halfway source
+ * lies outside the lattice stays an open-boundary unknown. */
+static void interpolated_bounce_back(orc *o, int outlet)
+{
+    const orc_params *p = &o->p;
+    const int Q = p->q;
+    const int64_t N = o->ncell;
+    const double q = p->wall_dist;
+    for (int64_t w = 0; w < o->nwall; ++w) {
+        const int64_t cell = o->wB[w];
+        const int side = o->wside[w];
+        const int x = (int)(cell % p->nx);
+        if (p->flow == ORC_PLATE && (x == p->nx - 1) != (outlet != 0)) continue;
+        double rho_w = 0.0;
+        for (int k = 0; k < Q; ++k) rho_w += o->fpost[k * N + cell];
+        for (int k = 0; k < Q; ++k) {
+            const int *ck = &o->c[3 * k];
+            if (ck[1] != side) continue; /* k points into the wall */
+            const int r = o->opp[k];
+            if (!crossing_is_wall(o, x, side, o->c[3 * r])) continue;
+            const int sx = x - o->c[3 * r];
+            if (p->flow == ORC_PLATE && (sx < 0 || sx >= p->nx)) continue;
+            const double cu = ck[0] * o->uw[3 * w] + ck[1] * o->uw[3 * w + 1] + ck[2] * o->uw[3 * w + 2];
+            const double corr = 2.0 * o->w[k] * rho_w * cu / CS2;
+            const double fkB = o->fpost[k * N + cell], fkF = o->fnew[k * N + cell];
+            const double frB = o->fpost[r * N + cell];
+            double fr;
+            if (p->bb_interp == ORC_IBB_BOUZIDI) {
+                if (q < 0.5)
+                    fr = 2.0 * q * fkB + (1.0 - 2.0 * q) * fkF - corr;
+                else
+                    fr = fkB / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * frB - corr / (2.0 * q);
+            } else {
+                /* linear interpolation to the wall point, reflection there,
+                 * linear interpolation back to B through F (Yu) */
+                const double frW = q * fkB + (1.0 - q) * fkF - corr;
+                fr = frW + q / (1.0 + q) * (frB - frW);
+            }
+            o->fnew[r * N + cell] = fr;
+        }
+    }
 }
 
 static void stream(orc *o)
@@ -606,6 +666,8 @@ static void stream(orc *o)
                     o->fnew[i * N + cell] = val;
                 }
             }
+    const int interp = p->bb_interp != ORC_IBB_HALFWAY;
+    if (interp) interpolated_bounce_back(o, 0);
     if (p->flow == ORC_PLATE) {
         /* outlet: the unknown populations are copied from the streamed
          * populations of the column x = nx - 2 */
@@ -622,6 +684,7 @@ static void stream(orc *o)
             orc_zou_he_west(f, p->u_inlet);
             for (int i = 0; i < 9; ++i) o->fnew[i * N + c0] = f[i];
         }
+        if (interp) interpolated_bounce_back(o, 1);
     }
 }
 

@@ -31,6 +31,11 @@ extern "C" {
 #define ORC_HRFD 2     /* hybrid regularized reconstruction (eq. 19, 23, 26-28) */
 #define ORC_CAI_DEGRIGNY 3 /* regularized reconstruction with the gradient of eq. 29 (eq. 30) */
 
+/* bounce-back link rule (ORC_BB_FIXED / ORC_BB_SLIP) */
+#define ORC_IBB_HALFWAY 0 /* halfway: the wall midway between nodes (eq. 31) */
+#define ORC_IBB_BOUZIDI 1 /* Bouzidi's interpolated rule, wall at wall_dist from B (eq. 36) */
+#define ORC_IBB_YU 2      /* Yu's interpolated rule through the wall point (eq. 37) */
+
 /* collision operators */
 #define ORC_BGK 0 /* BGK with Guo forcing */
 #define ORC_CM 1  /* central-moment operator of eq. 7 */
@@ -58,6 +63,9 @@ typedef struct orc_params {
     double kappa, B;     /* wall law constants (kappa also the SA kappa) */
     double beta;         /* HRFD blending parameter, eq. 27 */
     double cb1, cb2, sigma, cw2, cw3, cv1, rlim; /* SA constants, eq. 10-14 */
+    int32_t bb_interp;   /* ORC_IBB_* (bounce-back schemes) */
+    int32_t pad_;
+    double wall_dist;    /* distance from the first node B to the wall (1/2: halfway) */
 } orc_params;
 
 typedef struct orc orc;

@@ -649,3 +649,110 @@ def test_cm_forcing_gives_shifted_maxwellian(q):
                 continue
             ex = rho * np.prod([M(e[a], v[a]) for a in range(3)])
             assert abs(fp @ mono - ex) < 2e-6, (e, fp @ mono - ex)
+
+
+# ----------------------------------------------- interpolated bounce-back -----
+def _ibb_run(ny, q, interp, force=0.0, u_top=0.0, tau=0.8, steps=None):
+    nu = (tau - 0.5) / 3
+    H = ny - 1 + 2 * q
+    p = O.params(q=9, nx=3, ny=ny, nz=1, nu=nu, force=(force, 0, 0), sa_on=0,
+                 scheme=O.BB_FIXED, bb_interp=interp, wall_dist=q, wall_u_top=(u_top, 0, 0))
+    o = O.Oracle(p, np.zeros((2, 1, ny, 3)))
+    o.step(steps or int(4 * H * H / nu))
+    return o.u()[0, 0, :, 1], np.arange(ny) + q, H, nu
+
+
+@pytest.mark.parametrize("interp", [O.IBB_BOUZIDI, O.IBB_YU])
+@pytest.mark.parametrize("q", [0.2, 0.5, 0.7])
+def test_ibb_couette_exact(interp, q):
+    """eq. 36 and eq. 37 interpolate linearly along the link, so plane Couette
+    flow with the walls at distance q from the first and last nodes is
+    reproduced exactly: u = U (y + q) / (ny - 1 + 2q)."""
+    U = 0.01
+    u, y, H, _ = _ibb_run(8, q, interp, u_top=U)
+    assert np.abs(u - U * y / H).max() < 1e-11 * U
+
+
+@pytest.mark.parametrize("interp", [O.IBB_BOUZIDI, O.IBB_YU])
+@pytest.mark.parametrize("q", [0.2, 0.7])
+def test_ibb_poiseuille_second_order(interp, q):
+    """Poiseuille flow between walls placed off the halfway position converges
+    to g/(2 nu) y (H - y) at second order in the lattice spacing."""
+    errs = []
+    for ny in (8, 16, 32):
+        H = ny - 1 + 2 * q
+        nu = 0.1
+        g = 8 * nu * 1e-3 / H ** 2
+        u, y, H, nu = _ibb_run(ny, q, interp, force=g)
+        ex = g / (2 * nu) * y * (H - y)
+        errs.append(np.linalg.norm(u - ex) / np.linalg.norm(ex))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all((orders > 1.7) & (orders < 2.3)), (errs, orders)
+
+
+def test_bouzidi_at_half_is_halfway_bounce_back():
+    """At q = 1/2 eq. 36 reduces to the halfway rule of eq. 31 (both
+    branches): a turbulent slip-velocity channel is bitwise the same."""
+    lat = OU.channel_lattice(2000.0, 8, 0.05)
+    rng = np.random.Generator(np.random.PCG64(0))
+    u0 = np.zeros((2, 1, 16, 4))
+    u0[0] = lat["u_b"]
+    u0 += 1e-3 * (2 * rng.random(u0.shape) - 1)
+    out = []
+    for interp in (O.IBB_HALFWAY, O.IBB_BOUZIDI):
+        p = O.params(q=9, nx=4, ny=16, nu=lat["nu"], force=(lat["g"] * 20, 0, 0),
+                     scheme=O.BB_SLIP, bb_interp=interp, wall_dist=0.5)
+        o = O.Oracle(p, u0)
+        o.step(60)
+        out.append((o.u(), o.f()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_yu_keeps_the_f_node_at_half():
+    """Unlike eq. 36, eq. 37 at q = 1/2 is not the halfway rule (the reflected
+    population keeps a share of the one at F), yet it still converges."""
+    ny, q = 16, 0.5
+    H = ny - 1 + 2 * q
+    g = 8 * 0.1 * 1e-3 / H ** 2
+    ub, y, H, nu = _ibb_run(ny, q, O.IBB_BOUZIDI, force=g)
+    uy, _, _, _ = _ibb_run(ny, q, O.IBB_YU, force=g)
+    ex = g / (2 * nu) * y * (H - y)
+    assert np.abs(uy - ub).max() > 1e-6 * ex.max()
+    assert np.linalg.norm(uy - ex) / np.linalg.norm(ex) < 5e-3
+
+
+@pytest.mark.parametrize("q", [0.5, 0.3, 0.8])
+def test_sa_wall_distance_follows_the_wall_position(q):
+    """With the walls q from the first and last nodes, node y sits y + q from
+    the bottom wall: from rest and a uniform nu_tilde the first step changes
+    nu_tilde by the SA right-hand side (pinned separately) at that distance,
+    here only destruction (no shear, no gradients)."""
+    ny, nu, nt0 = 12, 1e-3, 3e-3
+    p = O.params(q=9, nx=3, ny=ny, nz=1, nu=nu, sa_on=1, scheme=O.BB_FIXED,
+                 bb_interp=O.IBB_BOUZIDI if q != 0.5 else O.IBB_HALFWAY, wall_dist=q,
+                 nut_init_ratio=nt0 / nu)
+    o = O.Oracle(p, np.zeros((2, 1, ny, 3)))
+    o.step(1)
+    nt = o.nt()[0, :, 1]
+    z3 = np.zeros(3)
+    for y in range(2, ny - 2):  # neighbours away from the Dirichlet wall nodes
+        d = min(y + q, ny - 1 - y + q)
+        ex = nt0 + O.sa_rhs(p, 2, nt0, [nt0] * 3, [nt0] * 3, z3, z3, z3, d)
+        assert abs(nt[y] - ex) < 1e-15 * nt0, (y, nt[y], ex)
+
+
+@pytest.mark.parametrize("q", [0.5, 0.3, 0.8])
+def test_wall_function_reference_node_follows_the_wall_position(q):
+    """A uniform shear u = S (y + q) measured from a wall q below the first
+    node: with the SA law (u+ = y+ to O(y+^5) near the wall) the wall function,
+    reading u at the second node (y_F = 1 + q), returns the exact friction
+    velocity sqrt(nu S) at every wall cell."""
+    ny, nu, S = 12, 1e-2, 1e-8
+    y = np.arange(ny) + q
+    u0 = np.zeros((2, 1, ny, 3))
+    u0[0, 0] = (S * np.minimum(y, ny - 1 + 2 * q - y))[:, None]
+    p = O.params(q=9, nx=3, ny=ny, nz=1, nu=nu, sa_on=1, scheme=O.BB_SLIP, law=O.SA_LAW,
+                 bb_interp=O.IBB_BOUZIDI if q != 0.5 else O.IBB_HALFWAY, wall_dist=q)
+    o = O.Oracle(p, u0)
+    ut = o.wall()["utau"]
+    assert np.abs(ut / math.sqrt(nu * S) - 1).max() < 1e-9, ut
