@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define LBM_PARAMS_VERSION 1
+#define LBM_PARAMS_VERSION 2
 
 enum {
     LBM_OK = 0,
@@ -99,6 +99,16 @@ typedef enum {
     LBM_WALL_CAI_DEGRIGNY = 3
 } lbm_wall_scheme_t;
 
+/* Link rule of LBM_WALL_FIXED_BB / LBM_WALL_SLIP_BB (Sec. 3.2).
+ * LBM_IBB_HALFWAY: the wall midway between nodes, eq. 31.
+ * LBM_IBB_BOUZIDI: Bouzidi's interpolated bounce-back, eq. 36, with the wall
+ *   at wall_dist from the first node along every wall-crossing link.
+ * LBM_IBB_YU: Yu's rule, eq. 37: the incoming population is interpolated
+ *   linearly to the wall point, reflected there with eq. 31's moving-wall
+ *   term, and interpolated back to the node through the second node F.
+ * The HRFD and Cai-Degrigny schemes use halfway walls (wall_dist = 1/2). */
+typedef enum { LBM_IBB_HALFWAY = 0, LBM_IBB_BOUZIDI = 1, LBM_IBB_YU = 2 } lbm_ibb_t;
+
 /* Collision operators (Sec. 2.1).
  * LBM_COLL_BGK: single relaxation time omega = 1/tau_eff with the second-order
  *   equilibrium and Guo forcing weighted by (1 - omega/2).
@@ -139,6 +149,12 @@ typedef struct lbm_params {
     double cb1, cb2, sigma, cw2, cw3, cv1, rlim; /* SA constants (after eq. 14) */
     double store_shift_u; /* populations are stored as f - f_eq(rho0, (store_shift_u, 0, 0));
                              0 (default) stores f - w rho0 */
+    int32_t bb_interp;    /* link rule of the bounce-back schemes: lbm_ibb_t */
+    int32_t pad_;
+    double wall_dist;     /* distance q of the first node from the wall, in (0, 1]:
+                             1/2 (default) for halfway walls, any value with
+                             LBM_IBB_BOUZIDI / LBM_IBB_YU; the wall function then
+                             reads B at y_B = q and F at y_F = 1 + q (Sec. 3.1) */
 } lbm_params_t;
 
 /* Reduction result (all double).  mass = sum rho, momentum = sum rho u over all

@@ -560,14 +560,15 @@ void orc_destroy(orc *o)
 /* Does a population that reaches cell (x, y) through the wall-normal face
  * side (-1 bottom, +1 top) with x-velocity cx reflect off a wall (1) or a
  * symmetry plane (0)?  Channel: walls.  Plate: the top is a symmetry plane;
- * at the bottom the point X = x + 1/2 - d_w cx where the outgoing link meets
- * the wall plane decides: on the plate (X >= plate_start, the leading-edge
- * point included) it is a wall.  For d_w = 1/2: 2x + 1 - cx >= 2 plate_start. */
+ * at the bottom the crossing point X = x + 1/2 - cx/2 decides: on the plate
+ * (X >= plate_start, the leading-edge point included) it is a wall.  The
+ * halfway crossing point is used whatever the wall distance: a link and its
+ * specular image then always agree, so streaming stays a bijection. */
 static int crossing_is_wall(const orc *o, int x, int side, int cx)
 {
     if (o->p.flow == ORC_CHANNEL) return 1;
     if (side > 0) return 0;
-    return x + 0.5 - o->p.wall_dist * cx >= (double)o->p.plate_start;
+    return 2 * x + 1 - cx >= 2 * o->p.plate_start;
 }
 
 /* Interpolated bounce-back at the wall cells (eq. 36, eq. 37) with the wall

@@ -145,7 +145,7 @@ template <int Q> __host__ __device__ constexpr int xslot(int i)
 // the wall links (eq. 31) and symmetry planes resolved; the open-boundary
 // unknowns of the plate are left at 0 for plate_edges.
 // ---------------------------------------------------------------------------
-template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD>
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool IBB = false>
 __device__ __forceinline__ void gather(const KP &P, const Cell &C, T *f)
 {
     using SS = Stor<S>;
@@ -184,10 +184,54 @@ __device__ __forceinline__ void gather(const KP &P, const Cell &C, T *f)
         if (shifted)
             v += !ycross ? shift_off<Q, T>(i, r0, Us)
                          : (wall ? shift_off<Q, T>(opp<Q>(i), r0, Us) : shift_off<Q, T>(mir<Q>(i), r0, Us));
-        // eq. 31: f_i = f*_opp(i) + 2 w_i rho_w (c_i . u_w) / cs2
-        if (!HRFD && wall && wi >= 0)
+        // eq. 31: f_i = f*_opp(i) + 2 w_i rho_w (c_i . u_w) / cs2 (halfway links;
+        // interpolated links keep f*_opp(i) here and are finished by ibb_links)
+        if (!HRFD && wall && wi >= 0 && (!IBB || P.bb_interp == IBB_HALFWAY))
             v += (T)(6.0 * wgt<Q>(i)) * rho_w * ((T)ccx * uwv[0] + (T)ccy * uwv[1] + (T)ccz * uwv[2]);
         f[i] = (active && !xopen) ? v : (T)0;
+    });
+}
+
+// Interpolated bounce-back (eq. 36 Bouzidi, eq. 37 Yu) at a wall cell, the
+// wall at q = d_w from B along every wall link.  On entry f[r] of a wall link r
+// holds f*_k(B) (k = opp(r), the population that left B towards the wall) and
+// f[k] holds f_k(B, t+1) = f*_k(F), arrived from F = B - c_k; ibuf keeps B's
+// post-collision populations of the previous step, f*_r(B) = f_r(F, t+1).
+// On the plate the outlet column is treated after the outlet copy and the
+// others before it; a reflection whose halfway source lies outside the
+// lattice stays an open-boundary unknown.
+template <int Q, typename T, bool PLATE>
+__device__ __forceinline__ void ibb_links(const KP &P, const Cell &C, T *f)
+{
+    const int64_t wi = C.wi;
+    if (P.bb_interp == IBB_HALFWAY || wi < 0) return;
+    const T q = (T)P.wall_dist;
+    const T rho_w = (T)P.wrho[wi];
+    const T uwv[3] = {(T)P.uw[wi], (T)P.uw[P.nwall + wi], (T)P.uw[2 * P.nwall + wi]};
+    const double *fr_prev = P.ibuf + wi * Q;
+    const int side = C.bottom ? -1 : 1;  // wall below / above the cell
+    const bool bouzidi = P.bb_interp == IBB_BOUZIDI;
+    sfor<Q>([&](auto ic) {
+        constexpr int r = decltype(ic)::value;  // leaves the wall
+        constexpr int k = opp<Q>(r);
+        constexpr int crx = cx<Q>(r), cry = cy<Q>(r), crz = cz<Q>(r);
+        if (cry != -side) return;
+        if (!(side < 0 ? bottom_is_wall(P, C.x, -crx) : P.flow == FLOW_CHANNEL)) return;
+        if (PLATE && (C.x - crx < 0 || C.x - crx >= P.nx)) return;
+        // eq. 31's moving-wall term, 2 w rho_w (c_r . u_w) / cs2
+        const T m = (T)(6.0 * wgt<Q>(r)) * rho_w * ((T)crx * uwv[0] + (T)cry * uwv[1] + (T)crz * uwv[2]);
+        const T fkB = f[r], fkF = f[k], frB = (T)fr_prev[r];
+        T v;
+        if (bouzidi) {
+            if (q < (T)0.5)
+                v = (T)2 * q * fkB + ((T)1 - (T)2 * q) * fkF + m;
+            else
+                v = fkB / ((T)2 * q) + ((T)2 * q - (T)1) / ((T)2 * q) * frB + m / ((T)2 * q);
+        } else {
+            const T frW = q * fkB + ((T)1 - q) * fkF + m;  // at the wall point
+            v = frW + q / ((T)1 + q) * (frB - frW);
+        }
+        f[r] = v;
     });
 }
 
@@ -208,7 +252,7 @@ template <typename T> __device__ __forceinline__ void zou_he(const KP &P, T *f)
 // velocity, wall density and the Spalart-Allmaras update of one cell.
 // rd: ping-pong index of u^{n-1} / nu_tilde^n; results go to rd ^ 1.
 // ---------------------------------------------------------------------------
-template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false>
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false, bool IBB = false>
 __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f, S *lds = nullptr)
 {
     constexpr int D = Lat<Q>::D;
@@ -315,6 +359,9 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f,
             f[i] = f[i] - omega * (f[i] - feqd) + src;
         });
     }
+    // post-collision populations of a wall cell for its interpolated links
+    if (IBB && P.bb_interp != IBB_HALFWAY && wi >= 0)
+        sfor<Q>([&](auto ic) { P.ibuf[wi * Q + decltype(ic)::value] = (double)f[decltype(ic)::value]; });
     // ---- store (AA pattern) ---------------------------------------------------
     sfor<Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
@@ -393,7 +440,9 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f,
 // a BLK-thread block.  Plate blocks must be aligned to the right end of a row
 // (columns nx-2 and nx-1 in one block) for the outlet exchange through LDS.
 // ---------------------------------------------------------------------------
-template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false>
+// IBB: interpolated bounce-back links may be present (else the halfway rule
+// is compiled in alone, keeping the common kernels lean).
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false, bool IBB = false>
 __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, int z, bool active)
 {
     const int nx = P.nx;
@@ -404,8 +453,9 @@ __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, i
         __shared__ S lds[nxdirs<Q>() * BLK];
         T f[Q];
         if (active) {
-            gather<Q, S, T, ODD, PLATE, HRFD>(P, C, f);
-            finish<Q, S, T, ODD, PLATE, HRFD, CMC, true>(P, C, rd, f, lds);
+            gather<Q, S, T, ODD, PLATE, HRFD, IBB>(P, C, f);
+            if constexpr (IBB && !HRFD) ibb_links<Q, T, false>(P, C, f);
+            finish<Q, S, T, ODD, PLATE, HRFD, CMC, true, IBB>(P, C, rd, f, lds);
         }
         __syncthreads();
         S *__restrict__ A = (S *)P.pops;
@@ -422,7 +472,9 @@ __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, i
         return;
     }
     T f[Q];
-    if (active) gather<Q, S, T, ODD, PLATE, HRFD>(P, C, f);
+    if (active) gather<Q, S, T, ODD, PLATE, HRFD, IBB>(P, C, f);
+    if constexpr (IBB && !HRFD)
+        if (active && (!PLATE || x != nx - 1)) ibb_links<Q, T, PLATE>(P, C, f);
     if (PLATE) {
         // outlet: unknown populations copied from column nx-2 (through LDS)
         __shared__ T xch[3][BLK];
@@ -436,11 +488,12 @@ __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, i
             f[2] = xch[0][tid - 1];
             f[6] = xch[1][tid - 1];
             f[8] = xch[2][tid - 1];
+            if constexpr (IBB && !HRFD) ibb_links<Q, T, PLATE>(P, C, f);
         }
         if (active && x == 0) zou_he(P, f);
     }
     if (!active) return;
-    finish<Q, S, T, ODD, PLATE, HRFD, CMC>(P, C, rd, f);
+    finish<Q, S, T, ODD, PLATE, HRFD, CMC, false, IBB>(P, C, rd, f);
 }
 
 // plate mapping: rows aligned to the right end, nseg blocks per row
@@ -455,7 +508,7 @@ __device__ __forceinline__ void plate_block(int nx, int64_t b, int tid, int &x, 
 // ---------------------------------------------------------------------------
 // k_step: one fused LBM-RANS step, one thread per cell.
 // ---------------------------------------------------------------------------
-template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC>
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool IBB>
 __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
 {
     const int nx = P.nx, ny = P.ny;
@@ -475,7 +528,7 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         x = (int)(seg * BLK) + tid;
         active = x < nx;
         if constexpr (ODD && !PLATE && LBM_XSTAGE) {
-            cell_update<Q, S, T, ODD, PLATE, HRFD, CMC, true>(P, rd, x, y, z, active);
+            cell_update<Q, S, T, ODD, PLATE, HRFD, CMC, true, IBB>(P, rd, x, y, z, active);
             return;
         }
     } else if (!PLATE) {
@@ -491,7 +544,7 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         z = 0;
         active = x >= 0;
     }
-    cell_update<Q, S, T, ODD, PLATE, HRFD, CMC>(P, rd, x, y, z, active);
+    cell_update<Q, S, T, ODD, PLATE, HRFD, CMC, false, IBB>(P, rd, x, y, z, active);
 }
 
 // ---------------------------------------------------------------------------
@@ -514,8 +567,8 @@ template <int D, typename T> __device__ __forceinline__ void wall_cell(const KP 
         x = P.plate_start + (int)w;
         z = 0;
     }
-    const int yB = side < 0 ? 0 : ny - 1;
-    const int64_t B = x + (int64_t)nx * (yB + (int64_t)ny * z);
+    const int yrow = side < 0 ? 0 : ny - 1;
+    const int64_t B = x + (int64_t)nx * (yrow + (int64_t)ny * z);
     const int64_t F = B - side * sy;
     const T *u = (const T *)P.u[wr];
     const double uFx = (double)u[F], uFz = D == 3 ? (double)u[2 * N + F] : 0.0;
@@ -526,8 +579,10 @@ template <int D, typename T> __device__ __forceinline__ void wall_cell(const KP 
         tx = uFx / ut;
         tz = uFz / ut;
     }
-    const double utau = solve_utau(P, ut, 1.5, P.utau[w]);
-    const double yBp = 0.5 * utau / P.nu;
+    // B and F sit d_w and 1 + d_w from the wall (Sec. 3.1; d_w = 1/2 halfway)
+    const double yB = P.wall_dist, yF = 1.0 + P.wall_dist;
+    const double utau = solve_utau(P, ut, yF, P.utau[w]);
+    const double yBp = yB * utau / P.nu;
     double uw[3] = {0.0, 0.0, 0.0};
     if (P.scheme == WALL_FIXED) {
         const double *s = side < 0 ? P.wall_u_bottom : P.wall_u_top;
@@ -535,8 +590,8 @@ template <int D, typename T> __device__ __forceinline__ void wall_cell(const KP 
         uw[1] = s[1];
         uw[2] = s[2];
     } else if (P.scheme == WALL_SLIP) {
-        // eq. 35 with nu_t|B = nu kappa y_B+ and Delta_w = y_B = 1/2
-        const double s = utau * utau * 0.5 / (P.nu * (1.0 + P.kappa * yBp));
+        // eq. 35 with nu_t|B = nu kappa y_B+ and Delta_w = y_B
+        const double s = utau * utau * yB / (P.nu * (1.0 + P.kappa * yBp));
         uw[0] = uBx - s * tx;
         uw[2] = uBz - s * tz;
     } else {
@@ -668,12 +723,15 @@ __global__ void __launch_bounds__(BLK) k_init(KP P, const double *u0, double ux0
     S *A = (S *)P.pops;
     const int64_t row = cell / P.nx;
     const int x = (int)(cell - row * P.nx);
+    // the wall cells' previous post-collision populations (interpolated links)
+    const int64_t wi = P.bb_interp != IBB_HALFWAY ? wall_index(P, x, (int)(row % P.ny), (int)(row / P.ny)) : -1;
     sfor<Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const double cu = cx<Q>(i) * u[0] + cy<Q>(i) * u[1] + cz<Q>(i) * u[2];
         const double fd = wgt<Q>(i) * P.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
         const double sh = P.shift_u != 0.0 ? (double)shift_off<Q, double>(i, P.rho0, P.shift_u) : 0.0;
         A[pidx<Q>(P.nx, opp<Q>(i), x, row)] = SS::st((T)(fd - sh));
+        if (wi >= 0) P.ibuf[wi * Q + i] = fd;
     });
     T *u_0 = (T *)P.u[0], *us = (T *)P.usnap;
     for (int a = 0; a < D; ++a) {
@@ -826,7 +884,8 @@ __device__ __forceinline__ void serve_cells(const KP &P, int rd, T (*xch)[SERVE_
         for (int y = threadIdx.x; y < P.ny; y += SBLK) {
             const Cell Cn = make_cell<9, true>(P, nx - 2, y, 0, true);
             T g[9];
-            gather<9, S, T, ODD, true, HRFD>(P, Cn, g);
+            gather<9, S, T, ODD, true, HRFD, !HRFD>(P, Cn, g);
+            if (!HRFD) ibb_links<9, T, true>(P, Cn, g);
             xch[0][y] = g[2];
             xch[1][y] = g[6];
             xch[2][y] = g[8];
@@ -837,16 +896,18 @@ __device__ __forceinline__ void serve_cells(const KP &P, int rd, T (*xch)[SERVE_
         const int y = (int)(cell / nx), x = (int)(cell - (int64_t)y * nx);
         const Cell C = make_cell<9, PLATE>(P, x, y, 0, true);
         T f[9];
-        gather<9, S, T, ODD, PLATE, HRFD>(P, C, f);
+        gather<9, S, T, ODD, PLATE, HRFD, !HRFD>(P, C, f);
+        if (!HRFD && (!PLATE || x != nx - 1)) ibb_links<9, T, PLATE>(P, C, f);
         if (PLATE) {
             if (x == nx - 1) {
                 f[2] = xch[0][y];
                 f[6] = xch[1][y];
                 f[8] = xch[2][y];
+                if (!HRFD) ibb_links<9, T, PLATE>(P, C, f);
             }
             if (x == 0) zou_he(P, f);
         }
-        finish<9, S, T, ODD, PLATE, HRFD, CMC>(P, C, rd, f);
+        finish<9, S, T, ODD, PLATE, HRFD, CMC, false, !HRFD>(P, C, rd, f);
     }
 }
 
@@ -933,9 +994,9 @@ __device__ __forceinline__ void mstep_body(const KP &P, int rd, int64_t lb)
             int x, y;
             plate_block(P.nx, lb, tid, x, y);
             if (P.scheme >= WALL_HRFD)
-                cell_update<Q, S, T, ODD, true, true, CMC>(P, rd, x, y, 0, x >= 0);
+                cell_update<Q, S, T, ODD, true, true, CMC, false, false>(P, rd, x, y, 0, x >= 0);
             else
-                cell_update<Q, S, T, ODD, true, false, CMC>(P, rd, x, y, 0, x >= 0);
+                cell_update<Q, S, T, ODD, true, false, CMC, false, true>(P, rd, x, y, 0, x >= 0);
         }
         return;
     }
@@ -945,11 +1006,11 @@ __device__ __forceinline__ void mstep_body(const KP &P, int rd, int64_t lb)
     const int x = active ? (int)(cell - r * P.nx) : 0, y = (int)(r % P.ny), z = (int)(r / P.ny);
     if constexpr (Q == 9) {
         if (P.scheme >= WALL_HRFD) {
-            cell_update<Q, S, T, ODD, false, true, CMC>(P, rd, x, y, z, active);
+            cell_update<Q, S, T, ODD, false, true, CMC, false, false>(P, rd, x, y, z, active);
             return;
         }
     }
-    cell_update<Q, S, T, ODD, false, false, CMC>(P, rd, x, y, z, active);
+    cell_update<Q, S, T, ODD, false, false, CMC, false, true>(P, rd, x, y, z, active);
 }
 
 template <int Q, typename S, typename T, bool CMC>
@@ -1059,7 +1120,7 @@ int storage_bytes(int precision)
 }
 
 struct Layout {
-    int64_t pops, u0, u1, nt0, nt1, usnap, utau, tdir, uw, wrho, ubwf, gan, partials, result, total;
+    int64_t pops, u0, u1, nt0, nt1, usnap, utau, tdir, uw, wrho, ubwf, gan, partials, result, ibuf, total;
 };
 
 int64_t nwall_of(int flow, int nx, int nz, int plate_start)
@@ -1092,6 +1153,7 @@ bool make_layout(int Q, int nx, int ny, int nz, const lbm_params_t *p, Layout *L
     L->gan = o; o = align256(o + (nw + 1) * 8);
     L->partials = o; o = align256(o + (int64_t)RED_BLOCKS * NRED * 8);
     L->result = o; o = align256(o + 32 * 8);
+    L->ibuf = o; o = align256(o + (p->bb_interp != LBM_IBB_HALFWAY ? (int64_t)Q * nw * 8 : 0));
     L->total = o;
     return true;
 }
@@ -1122,10 +1184,14 @@ namespace {
 
 template <int Q, typename S, typename T> struct Impl {
     static constexpr int D = Lat<Q>::D;
-    template <bool PLATE, bool HRFD> static void (*pick(bool odd, bool cm))(KP, int)
+    template <bool PLATE, bool HRFD, bool IBB> static void (*pick(bool odd, bool cm))(KP, int)
     {
-        if (cm) return odd ? k_step<Q, S, T, true, PLATE, HRFD, true> : k_step<Q, S, T, false, PLATE, HRFD, true>;
-        return odd ? k_step<Q, S, T, true, PLATE, HRFD, false> : k_step<Q, S, T, false, PLATE, HRFD, false>;
+        if (cm) return odd ? k_step<Q, S, T, true, PLATE, HRFD, true, IBB> : k_step<Q, S, T, false, PLATE, HRFD, true, IBB>;
+        return odd ? k_step<Q, S, T, true, PLATE, HRFD, false, IBB> : k_step<Q, S, T, false, PLATE, HRFD, false, IBB>;
+    }
+    template <bool PLATE> static void (*pick_bb(bool odd, bool cm, bool ibb))(KP, int)
+    {
+        return ibb ? pick<PLATE, false, true>(odd, cm) : pick<PLATE, false, false>(odd, cm);
     }
     static int step(lbm *h, bool odd, int rd)
     {
@@ -1138,17 +1204,18 @@ template <int Q, typename S, typename T> struct Impl {
         else
             grid = dim3((unsigned)((P.ncell + BLK - 1) / BLK));
         const bool cm = h->p.collision == LBM_COLL_CM;
+        const bool ibb = h->p.bb_interp != LBM_IBB_HALFWAY;
         void (*kern)(KP, int) = nullptr;
         if constexpr (Q == 9) {
             if (plate) {
-                if (hrfd) kern = pick<true, true>(odd, cm);
-                else kern = pick<true, false>(odd, cm);
+                if (hrfd) kern = pick<true, true, false>(odd, cm);
+                else kern = pick_bb<true>(odd, cm, ibb);
             } else {
-                if (hrfd) kern = pick<false, true>(odd, cm);
-                else kern = pick<false, false>(odd, cm);
+                if (hrfd) kern = pick<false, true, false>(odd, cm);
+                else kern = pick_bb<false>(odd, cm, ibb);
             }
         } else {
-            kern = pick<false, false>(odd, cm);
+            kern = pick_bb<false>(odd, cm, ibb);
         }
         hipLaunchKernelGGL(kern, grid, dim3(BLK), 0, h->stream, P, rd);
         HIPCHK(hipGetLastError());
@@ -1238,6 +1305,11 @@ int check_params(int lattice, int nx, int ny, int nz, const lbm_params_t *p)
     if (!(p->rho0 > 0.0)) return fail(LBM_EINVAL, "rho0 must be > 0");
     if (p->reduce_every < 0) return fail(LBM_EINVAL, "reduce_every must be >= 0");
     if (p->collision != LBM_COLL_BGK && p->collision != LBM_COLL_CM) return fail(LBM_EINVAL, "unknown collision %d", p->collision);
+    if (p->bb_interp < LBM_IBB_HALFWAY || p->bb_interp > LBM_IBB_YU) return fail(LBM_EINVAL, "unknown bb_interp %d", p->bb_interp);
+    if (p->bb_interp != LBM_IBB_HALFWAY && p->scheme >= LBM_WALL_HRFD)
+        return fail(LBM_EINVAL, "interpolated links apply to the bounce-back schemes only");
+    if (p->bb_interp == LBM_IBB_HALFWAY ? p->wall_dist != 0.5 : !(p->wall_dist > 0.0 && p->wall_dist <= 1.0))
+        return fail(LBM_EINVAL, "wall_dist must be 1/2 for halfway walls and in (0, 1] otherwise");
     if ((int64_t)nx * ny * nz > (int64_t)1 << 40) return fail(LBM_EINVAL, "lattice too large");
     return LBM_OK;
 }
@@ -1297,6 +1369,9 @@ void fill_kp(lbm *h)
     k.ubwf = (double *)(b + L.ubwf);
     k.gan = (double *)(b + L.gan);
     k.partials = (double *)(b + L.partials);
+    k.ibuf = (double *)(b + L.ibuf);
+    k.bb_interp = p.bb_interp;
+    k.wall_dist = p.wall_dist;
     k.result = (double *)(b + L.result);
 }
 
@@ -1385,6 +1460,8 @@ void lbm_params_default(lbm_params_t *p)
     p->cw3 = 2.0;
     p->cv1 = 7.1;
     p->rlim = 10.0;
+    p->bb_interp = LBM_IBB_HALFWAY;
+    p->wall_dist = 0.5;
 }
 
 int64_t lbm_footprint(lbm_lattice_t lattice, int nx, int ny, int nz, const lbm_params_t *p)
@@ -1464,6 +1541,8 @@ int lbm_set_wall_bc(lbm_t *h, lbm_wall_scheme_t scheme, double beta)
     if (!h) return fail(LBM_ESTATE, "NULL handle");
     if (scheme < LBM_WALL_FIXED_BB || scheme > LBM_WALL_CAI_DEGRIGNY) return fail(LBM_EINVAL, "unknown wall scheme");
     if (scheme >= LBM_WALL_HRFD && h->Q != 9) return fail(LBM_EINVAL, "HRFD is D2Q9 only");
+    if (scheme >= LBM_WALL_HRFD && h->p.bb_interp != LBM_IBB_HALFWAY)
+        return fail(LBM_EINVAL, "interpolated links apply to the bounce-back schemes only");
     h->p.scheme = scheme;
     h->p.beta = beta;
     h->kp.scheme = scheme;

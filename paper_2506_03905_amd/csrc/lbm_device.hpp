@@ -168,10 +168,15 @@ struct KP {
     double *gan;         // nwall: analytic wall-normal gradient (u_tau^2/nu) du+/dy+ at B
     double *partials;    // reduction partials
     double *result;      // reduction result slots
+    double *ibuf;        // Q * nwall: post-collision populations of the wall cells (interpolated links)
+    double wall_dist;    // distance of the first node from the wall (1/2: halfway)
+    int bb_interp;       // IBB_HALFWAY / IBB_BOUZIDI / IBB_YU
+    int pad2_;
 };
 
 constexpr int FLOW_CHANNEL = 0, FLOW_PLATE = 1;
 constexpr int WALL_FIXED = 0, WALL_SLIP = 1, WALL_HRFD = 2, WALL_CD = 3;
+constexpr int IBB_HALFWAY = 0, IBB_BOUZIDI = 1, IBB_YU = 2;
 constexpr int LAW_REICHARDT = 0, LAW_SA = 1;
 
 // wall index of a boundary cell (or -1)
@@ -192,6 +197,11 @@ __device__ __forceinline__ int64_t wall_index(const KP &P, int x, int y, int z)
 // point included.  For a population arriving at x through the bottom face
 // with x-velocity cx_in, the emitting link is the one with cx_out = -cx_in
 // (bounce-back) or the mirrored one of the neighbour, both giving the same X.
+// A link leaving cell x of the bottom row with x-velocity cx_out crosses the
+// bottom at X = x + 1/2 + cx_out/2: a wall on the plate (X >= plate_start, the
+// leading-edge point included), a symmetry plane upstream.  The halfway
+// crossing point is used for every wall distance, so that a link and its
+// specular image agree and the AA streaming stays a bijection.
 __device__ __forceinline__ bool bottom_is_wall(const KP &P, int x, int cx_out)
 {
     if (P.flow == FLOW_CHANNEL) return true;
@@ -466,11 +476,15 @@ template <typename T> __device__ __forceinline__ T nut_of(const KP &P, T nt)
 }
 
 // distance to the closest wall of a cell centre (Sec. 2.2)
+// Distance to the closest wall: node y lies y + d_w above the bottom wall, the
+// channel's top wall d_w above node ny - 1; the plate's leading-edge point
+// sits at x = plate_start on the wall plane (node x at x + 1/2).
 template <typename T> __device__ __forceinline__ T wall_dist(const KP &P, int x, int y)
 {
-    T yc = (T)y + (T)0.5;
+    const T dw = (T)P.wall_dist;
+    T yc = (T)y + dw;
     if (P.flow == FLOW_CHANNEL) {
-        T yt = (T)P.ny - yc;
+        T yt = (T)(P.ny - 1 - y) + dw;
         return yc < yt ? yc : yt;
     }
     T dx = (T)P.plate_start - ((T)x + (T)0.5);

@@ -19,6 +19,7 @@ LBM_D2Q9, LBM_D3Q19 = 9, 19
 LBM_F64, LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2, 3
 LBM_FLOW_CHANNEL, LBM_FLOW_PLATE = 0, 1
 LBM_WALL_FIXED_BB, LBM_WALL_SLIP_BB, LBM_WALL_HRFD, LBM_WALL_CAI_DEGRIGNY = 0, 1, 2, 3
+LBM_IBB_HALFWAY, LBM_IBB_BOUZIDI, LBM_IBB_YU = 0, 1, 2
 LBM_LAW_REICHARDT, LBM_LAW_SA = 0, 1
 LBM_COLL_BGK, LBM_COLL_CM = 0, 1
 
@@ -46,6 +47,7 @@ class lbm_params_t(ctypes.Structure):
         ("beta", ctypes.c_double), ("cb1", ctypes.c_double), ("cb2", ctypes.c_double),
         ("sigma", ctypes.c_double), ("cw2", ctypes.c_double), ("cw3", ctypes.c_double),
         ("cv1", ctypes.c_double), ("rlim", ctypes.c_double), ("store_shift_u", ctypes.c_double),
+        ("bb_interp", ctypes.c_int32), ("pad_", ctypes.c_int32), ("wall_dist", ctypes.c_double),
     ]
 
 

@@ -85,6 +85,19 @@ def test_invalid_parameters_rejected(L):
     p = L.lbm_params_default(scheme=L.LBM_WALL_HRFD)
     with pytest.raises(L.LbmError, match="HRFD"):
         L.lbm_footprint(L.LBM_D3Q19, 16, 16, 4, p)
+    # interpolated links: bounce-back schemes only, the wall within one link;
+    # halfway links need the wall at 1/2
+    for kw in ({"bb_interp": 3}, {"bb_interp": L.LBM_IBB_BOUZIDI, "wall_dist": 0.0},
+               {"bb_interp": L.LBM_IBB_YU, "wall_dist": 1.5}, {"wall_dist": 0.3},
+               {"bb_interp": L.LBM_IBB_YU, "wall_dist": 0.3, "scheme": L.LBM_WALL_HRFD}):
+        p = L.lbm_params_default(**kw)
+        with pytest.raises(L.LbmError, match="bb_interp|wall_dist|interpolated"):
+            L.lbm_footprint(L.LBM_D2Q9, 4, 16, 1, p)
+    # the wall cells' populations are kept for interpolated links
+    base = L.lbm_footprint(L.LBM_D2Q9, 4, 16, 1, L.lbm_params_default())
+    ibb = L.lbm_footprint(L.LBM_D2Q9, 4, 16, 1,
+                          L.lbm_params_default(bb_interp=L.LBM_IBB_YU, wall_dist=0.3))
+    assert ibb >= base + 9 * 8 * 8
 
 
 def test_create_rejects_small_buffer_without_device(L):

@@ -27,19 +27,21 @@ def _torch_gpu():
 def _pair(q, nx, ny, nz, *, scheme, u0, nu, force=(0, 0, 0), flow=O.CHANNEL, plate_start=0,
           u_inlet=0.0, sa_on=1, law=O.REICHARDT, beta=0.28, precision="f64",
           wall_u_top=(0, 0, 0), collision=O.BGK, oracle_shape=None, oracle_u0=None,
-          store_shift_u=0.0):
+          store_shift_u=0.0, bb_interp=0, wall_dist=0.5):
     _torch_gpu()
     oq = dict(nx=nx, ny=ny, nz=nz)
     if oracle_shape is not None:
         oq = dict(zip(("nx", "ny", "nz"), oracle_shape))
     op = O.params(q=q, **oq, flow=flow, scheme=scheme, law=law, sa_on=sa_on,
                   plate_start=plate_start, nu=nu, force=force, u_inlet=u_inlet, beta=beta,
-                  wall_u_top=wall_u_top, collision=collision)
+                  wall_u_top=wall_u_top, collision=collision, bb_interp=bb_interp,
+                  wall_dist=wall_dist)
     o = O.Oracle(op, u0 if oracle_u0 is None else oracle_u0)
     gp = L.lbm_params_default(precision=L.PRECISION[precision], flow=flow, scheme=scheme,
                               law=law, sa_on=sa_on, plate_start=plate_start, nu=nu,
                               force=force, u_inlet=u_inlet, beta=beta, wall_u_top=wall_u_top,
-                              reduce_every=0, collision=collision, store_shift_u=store_shift_u)
+                              reduce_every=0, collision=collision, store_shift_u=store_shift_u,
+                              bb_interp=bb_interp, wall_dist=wall_dist)
     g = L.Lattice(q, nx, ny, nz, gp)
     g.lbm_set_velocity(u0)
     return o, g
@@ -111,6 +113,63 @@ def test_d3q19_channel_slip_bb_f64(steps):
     u0 = _channel_u0(19, nx, ny, nz, lat["u_bulk"])
     o, g = _pair(19, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
                  force=(lat["force"] * 10, 0, 0))
+    o.step(steps)
+    g.lbm_step(steps)
+    _compare_f64(o, g)
+
+
+@pytest.mark.parametrize("interp,q", [(O.IBB_BOUZIDI, 0.3), (O.IBB_BOUZIDI, 0.7),
+                                      (O.IBB_YU, 0.5), (O.IBB_YU, 0.25)])
+@pytest.mark.parametrize("steps", [1, 2, 41])
+def test_d2q9_interpolated_bounce_back_f64(interp, q, steps):
+    """Slip-velocity bounce-back with the walls q from the first nodes:
+    Bouzidi's rule (eq. 36, both branches) and Yu's (eq. 37)."""
+    lat = units.channel(3000.0, 8)
+    nx, ny = 4, 16
+    u0 = _channel_u0(9, nx, ny, 1, lat["u_bulk"])
+    o, g = _pair(9, nx, ny, 1, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"] * 20, 0, 0), collision=O.CM, bb_interp=interp, wall_dist=q)
+    o.step(steps)
+    g.lbm_step(steps)
+    _compare_f64(o, g)
+    assert np.abs(g.lbm_populations() - o.f()).max() < 1e-13
+
+
+@pytest.mark.parametrize("interp,q", [(O.IBB_BOUZIDI, 0.2), (O.IBB_YU, 0.8)])
+def test_interpolated_couette_fixed_walls_f64(interp, q):
+    """Laminar Couette flow with a moving top wall off the halfway position."""
+    ny, U = 10, 0.01
+    nu = 0.1
+    u0 = np.zeros((2, 1, ny, 3))
+    o, g = _pair(9, 3, ny, 1, scheme=O.BB_FIXED, u0=u0, nu=nu, sa_on=0,
+                 wall_u_top=(U, 0, 0), bb_interp=interp, wall_dist=q)
+    o.step(500)
+    g.lbm_step(500)
+    _compare_f64(o, g)
+
+
+@pytest.mark.parametrize("interp", [O.IBB_BOUZIDI, O.IBB_YU])
+def test_d3q19_interpolated_row_block_f64(interp):
+    """D3Q19 with interpolated links on the row-mapped, LDS-staged kernel."""
+    lat = units.channel(5000.0, 8)
+    nx, ny, nz = 128, 16, 4
+    u0 = _channel_u0(19, nx, ny, nz, lat["u_bulk"])
+    o, g = _pair(19, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"] * 10, 0, 0), collision=O.CM, bb_interp=interp, wall_dist=0.35)
+    o.step(9)
+    g.lbm_step(9)
+    _compare_f64(o, g)
+
+
+@pytest.mark.parametrize("q", [0.5, 0.3])
+@pytest.mark.parametrize("steps", [1, 2, 60])
+def test_d2q9_plate_yu_f64(q, steps):
+    """The flat plate with Yu's rule (the paper's choice there), including the
+    leading-edge links and the outlet corner."""
+    nx, ny, U = 300, 12, 0.05
+    u0 = inputs.channel_velocity(3, 2, 1, ny, nx, U, 1e-3)
+    o, g = _pair(9, nx, ny, 1, scheme=O.BB_SLIP, u0=u0, nu=0.03, flow=O.PLATE, plate_start=40,
+                 u_inlet=U, bb_interp=O.IBB_YU, wall_dist=q)
     o.step(steps)
     g.lbm_step(steps)
     _compare_f64(o, g)
