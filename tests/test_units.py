@@ -30,3 +30,18 @@ def test_table3_and_oracle_agree():
     for re_tau, n in ((2000.0, 32), (5000.0, 128), (5000.0, 24)):
         a, b = U.channel(re_tau, n), OU.channel_lattice(re_tau, n)
         assert abs(a["nu"] / b["nu"] - 1) < 1e-14 and abs(a["force"] / b["g"] - 1) < 1e-14
+
+
+def test_replication_cases_are_consistent():
+    """The channel studies: Table 3's grid (Re_tau 4200, N = 5 ... 40) with
+    y_B+ = Re_tau / (2N) for halfway walls, and a force that balances the
+    target wall stress, F h = u_tau^2."""
+    from paper_2506_03905_amd import replicate as R
+    cs = R.cases(["grid", "reynolds", "beta", "wall"])
+    assert {c["n"] for c in cs if c["study"] == "grid"} == {5, 10, 20, 30, 40}
+    for c in cs:
+        ny, h, u_b, u_tau, p = R.lattice_of(c)
+        assert abs(p.force[0] * h - u_tau ** 2) < 1e-18
+        assert abs(u_tau * h / p.nu - c["re_tau"]) < 1e-9 * c["re_tau"]
+        if c["q"] == 0.5:
+            assert h == c["n"] and abs(0.5 * u_tau / p.nu - c["re_tau"] / (2 * c["n"])) < 1e-9
