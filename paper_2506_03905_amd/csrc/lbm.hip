@@ -38,7 +38,10 @@ using namespace lbmd;
 
 namespace {
 
-constexpr int BLK = 256;
+#ifndef LBM_BLK
+#define LBM_BLK 256
+#endif
+constexpr int BLK = LBM_BLK;  // threads per block of the per-cell kernels
 #ifndef LBM_XSTAGE
 #define LBM_XSTAGE 1
 #endif
