@@ -38,10 +38,7 @@ using namespace lbmd;
 
 namespace {
 
-#ifndef LBM_BLK
-#define LBM_BLK 256
-#endif
-constexpr int BLK = LBM_BLK;  // threads per block of the per-cell kernels
+constexpr int BLK = 256;  // threads per block of the per-cell kernels (128 and 512 measured slower)
 #ifndef LBM_XSTAGE
 #define LBM_XSTAGE 1
 #endif

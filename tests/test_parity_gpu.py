@@ -267,12 +267,17 @@ def test_d3q19_channel_reduced_precision(precision, tol, shift):
     assert ut_err < tol, ut_err
 
 
-def test_checkpoint_roundtrip_bitwise():
+@pytest.mark.parametrize("interp,q", [(O.IBB_HALFWAY, 0.5), (O.IBB_YU, 0.3)])
+def test_checkpoint_roundtrip_bitwise(interp, q):
+    """Save, continue, load into a second lattice, continue: bitwise equal
+    (the wall cells' kept populations of the interpolated links included)."""
     lat = units.channel(2000.0, 8)
     nx, ny = 4, 16
     u0 = _channel_u0(9, nx, ny, 1, lat["u_bulk"])
-    _, g = _pair(9, nx, ny, 1, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"], precision="f32")
-    _, h = _pair(9, nx, ny, 1, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"], precision="f32")
+    kw = dict(scheme=O.BB_SLIP, u0=u0, nu=lat["nu"], precision="f32", bb_interp=interp,
+              wall_dist=q)
+    _, g = _pair(9, nx, ny, 1, **kw)
+    _, h = _pair(9, nx, ny, 1, **kw)
     g.lbm_step(7)
     blob = g.lbm_save()
     g.lbm_step(9)

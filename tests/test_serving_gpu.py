@@ -82,6 +82,34 @@ def test_multi_lattice_fp64_matches_oracle(req):
     pool.close()
 
 
+def test_pool_interpolated_links_fp64_matches_oracle():
+    """Yu's rule on a plate and Bouzidi's on a channel, in both pool groups."""
+    _gpu()
+    cases = [("plate", 48, 1500.0, L.LBM_IBB_YU, 0.3), ("channel", 32, 2000.0, L.LBM_IBB_BOUZIDI, 0.7)]
+    pool = L.Pool(256 << 20, max_slots=8)
+    slots = []
+    for kind, ny, rt, interp, q in cases:
+        req = _req(0, kind, ny, rt, "slip_bb")
+        lat, nx, ny_, nz, p, _ = serving.request_lattice(req)
+        p.precision, p.bb_interp, p.wall_dist = L.LBM_F64, interp, q
+        slots.append((pool.lbm_pool_admit(lat, nx, ny_, nz, p, None, 0.0, 220), p, nx, ny_))
+    pool.lbm_pool_step(220)
+    for (slot, p, nx, ny), (kind, *_rest) in zip(slots, cases):
+        st = pool.lbm_pool_poll(slot)
+        assert st["steps"] == 220 and st["batched"] == (kind == "channel")
+        op = O.params(q=9, nx=nx, ny=ny, nz=1, flow=p.flow, scheme=p.scheme, law=p.law,
+                      sa_on=p.sa_on, plate_start=p.plate_start, nu=p.nu, force=tuple(p.force),
+                      u_inlet=p.u_inlet, beta=p.beta, collision=p.collision,
+                      bb_interp=p.bb_interp, wall_dist=p.wall_dist)
+        u0 = np.zeros((2, 1, ny, nx))
+        u0[0] = p.u_init[0]
+        o = O.Oracle(op, u0)
+        o.step(220)
+        ug = pool.lbm_pool_lattice(slot).lbm_moments()[1]
+        assert np.abs(ug - o.u()).max() / np.abs(o.u()).max() < 1e-10
+    pool.close()
+
+
 def test_multi_lattice_d3q19_fp64_matches_oracle():
     """A D3Q19 channel in the pool (large-lattice group) against the oracle."""
     _gpu()
