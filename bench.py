@@ -19,7 +19,11 @@ residual below 1e-8 or to the step cap, through the batched pool and then one
 at a time through the plain per-lattice path; it prints solves/s and p50/p99
 time-to-result for both.
 
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line: the metric, its value and unit, the timing contract
+fields, the workload, the roofline of the fused step kernel (algorithmic bytes
+per launch over its measured duration, against 8 TB/s, and the HBM traffic
+measured by the hardware counters when available) and the oracle's rate on
+the host for scale.
 """
 import argparse
 import json
@@ -68,6 +72,55 @@ def cpu_baseline(nx: int, ny: int, nz: int, lat: dict, steps: int, collision: st
     return {"value": nx * ny * nz * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{nx}x{ny}x{nz} slab of the same channel (same resolution, Re_tau, start), "
                       f"{steps} steps, FP64, 1 thread, {dt:.1f} s"}
+
+
+def timed_steps(g, steps: int, warmup: int):
+    """(ms for `steps` steps between HIP events on the lattice's stream, timing dict)."""
+    import torch
+
+    g.lbm_step(warmup)
+    torch.cuda.synchronize()
+    g.lbm_set_timing(True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    g.lbm_step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    tm = g.lbm_get_timing()
+    g.lbm_set_timing(False)
+    return e0.elapsed_time(e1), tm
+
+
+def plate_bench(args):
+    """The flat-plate workload: D2Q9 2048 x 256, U = 0.1, Re = 5e6 per L_ref
+    (992 cells), plate from column 64, CM + SA, slip BB or HRFD."""
+    import paper_2506_03905_amd.lbm as L
+
+    nx, ny = args.nx or 2048, args.ny or 256
+    ps, U = 64, 0.1
+    nu = U * ((nx - ps) / 2.0) / 5e6
+    p = L.lbm_params_default(precision=L.PRECISION[args.precision], flow=L.LBM_FLOW_PLATE,
+                             scheme=L.SCHEME[args.scheme], collision=L.LBM_COLL_CM, nu=nu,
+                             u_init=(U, 0, 0), u_inlet=U, u_ref=U, plate_start=ps, reduce_every=100)
+    g = L.Lattice(L.LBM_D2Q9, nx, ny, 1, p, device="cuda:0")
+    ms, tm = timed_steps(g, args.steps, args.warmup)
+    ncell = nx * ny
+    bpl = bytes_per_lup(9, args.precision)
+    k_ms = tm["step_ms"] / max(tm["step_launches"], 1)
+    achieved = bpl * ncell / (k_ms * 1e-3) / 1e9
+    out = {"metric": "MLUPS (D2Q9 flat plate)", "value": round(ncell * args.steps / (ms * 1e-3) / 1e6, 1),
+           "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms / args.steps, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+           "config": {"workload": f"2-D flat plate D2Q9 {nx}x{ny}, Re 5e6 per L_ref, CM + SA, "
+                                  f"{args.scheme}", "cells": ncell},
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                        "kernel": "k_step", "bytes_per_lup": bpl, "kernel_ms": round(k_ms, 4),
+                        "wall_kernel_ms": round(tm["wall_ms"] / max(tm["wall_launches"], 1), 4)}}
+    print(json.dumps(out), flush=True)
 
 
 def serving_bench(args):
@@ -133,9 +186,12 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", default="f32", choices=["f32", "f16", "bf16", "f64"])
-    ap.add_argument("--nx", type=int, default=512)
-    ap.add_argument("--ny", type=int, default=256)
-    ap.add_argument("--nz", type=int, default=256)
+    ap.add_argument("--plate", action="store_true",
+                    help="the 2-D flat plate (D2Q9 2048 x 256, CM) instead of the 3-D channel")
+    ap.add_argument("--scheme", default="slip_bb", choices=["slip_bb", "hrfd"])
+    ap.add_argument("--nx", type=int, default=None)
+    ap.add_argument("--ny", type=int, default=None)
+    ap.add_argument("--nz", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--collision", default="bgk", choices=["bgk", "cm"])
@@ -152,8 +208,8 @@ def main():
                     help="requests run sequentially (default: all)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU; multi-GPU runs are not part of this build "
-              "(see DESIGN.md for how the lattice would shard).", file=sys.stderr)
+        print("bench.py measures one GPU: the lattice is not sharded across GPUs here "
+              "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -182,7 +238,9 @@ def main():
     import paper_2506_03905_amd.lbm as L
     from paper_2506_03905_amd import inputs, units
 
-    nx, ny, nz = args.nx, args.ny, args.nz
+    if args.plate:
+        return plate_bench(args)
+    nx, ny, nz = args.nx or 512, args.ny or 256, args.nz or 256
     lat = units.channel(5000.0, ny // 2, 0.05)
     coll = {"bgk": L.LBM_COLL_BGK, "cm": L.LBM_COLL_CM}[args.collision]
     p = L.lbm_params_default(precision=L.PRECISION[args.precision], scheme=L.LBM_WALL_SLIP_BB,

@@ -1,5 +1,5 @@
 """Seeded synthetic inputs shared by the tests, the benchmark and the serving
-driver.  Only random numbers and shapes live here -- no step of the method.
+loop.  Only random numbers and shapes live here -- no step of the method.
 
 * ``perturbation(seed, D, nz, ny, nx, amp)``: velocity perturbation
   amp * xi with xi uniform in [-1, 1), drawn from numpy's PCG64 seeded with

@@ -403,10 +403,12 @@ def _invariant_channel(q, nx, ny, nz, precision, steps, collision=O.BGK, shift=0
 
 
 def _report(key, vals):
+    """Append the measured errors to $LBM_REPORT_DIR/precision_report.jsonl
+    when that directory is given."""
     import json
     import os
-    d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(d):
+    d = os.environ.get("LBM_REPORT_DIR")
+    if d and os.path.isdir(d):
         with open(os.path.join(d, "precision_report.jsonl"), "a") as fh:
             fh.write(json.dumps({"case": key, **vals}) + "\n")
 
