@@ -333,12 +333,12 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f,
     });
     const T rho = (T)P.rho0 + drho;
     const T Fx = (T)P.fx, Fy = (T)P.fy, Fz = (T)P.fz;
-    const T inv = (T)1 / rho;
+    const T inv = Num<T>::rcp(rho);
     const T ux = (jx + (T)0.5 * Fx) * inv, uy = (jy + (T)0.5 * Fy) * inv, uz = D == 3 ? (jz + (T)0.5 * Fz) * inv : (T)0;
 
     // ---- collision with tau_eff = 1/2 + (nu + nu_t)/cs2 -------------------------
     const T nut = P.sa_on ? nut_of<T>(P, nt0) : (T)0;
-    const T omega = (T)1 / ((T)0.5 + (T)3 * ((T)P.nu + nut));
+    const T omega = Num<T>::rcp((T)0.5 + (T)3 * ((T)P.nu + nut));
     if constexpr (CMC) {
         // central-moment operator, eq. 7
         const T uvec[3] = {ux, uy, uz}, Fv[3] = {Fx, Fy, Fz};

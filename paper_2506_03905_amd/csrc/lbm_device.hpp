@@ -208,6 +208,26 @@ __device__ __forceinline__ bool bottom_is_wall(const KP &P, int x, int cx_out)
     return 2 * x + 1 + cx_out >= 2 * P.plate_start;
 }
 
+// Reciprocal, division, square root and x^(1/6) of the cell update.  With
+// FP64 storage they stay correctly rounded (element-wise parity with the
+// oracle); the FP32 path uses the hardware approximations (about 1 ulp, far
+// inside its tolerance), which cut the instruction count of the update.
+template <typename T> struct Num {
+    static __device__ __forceinline__ T rcp(T x) { return (T)1 / x; }
+    static __device__ __forceinline__ T div(T a, T b) { return a / b; }
+    static __device__ __forceinline__ T sqrt_(T x) { return sqrt(x); }
+    static __device__ __forceinline__ T root6(T x) { return sqrt(cbrt(x)); }
+};
+template <> struct Num<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float root6(float x)
+    {
+        return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 6.0f));
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Wall laws (double).
 // ---------------------------------------------------------------------------
@@ -312,17 +332,18 @@ __device__ __forceinline__ T sa_rhs(const KP &P, T nt0, const T *ntm, const T *n
         S = fabs(g[1][0] - g[0][1]);
     } else {
         T wx = g[2][1] - g[1][2], wy = g[0][2] - g[2][0], wz = g[1][0] - g[0][1];
-        S = sqrt(wx * wx + wy * wy + wz * wz);
+        S = Num<T>::sqrt_(wx * wx + wy * wy + wz * wz);
     }
-    T chi = nt0 / nu, chi3 = chi * chi * chi, cv13 = (T)(P.cv1 * P.cv1 * P.cv1);
-    T fv1 = chi3 / (chi3 + cv13);
-    T fv2 = (T)1 - chi / ((T)1 + chi * fv1);
+    using N = Num<T>;
+    T chi = N::div(nt0, nu), chi3 = chi * chi * chi, cv13 = (T)(P.cv1 * P.cv1 * P.cv1);
+    T fv1 = N::div(chi3, chi3 + cv13);
+    T fv2 = (T)1 - N::div(chi, (T)1 + chi * fv1);
     T kd2 = k * k * d * d;
-    T St = S + nt0 / kd2 * fv2;
+    T St = S + N::div(nt0, kd2) * fv2;
     T Pr, r;
     if (St > (T)0) {
         Pr = (T)P.cb1 * St * nt0;
-        r = nt0 / (St * kd2);
+        r = N::div(nt0, St * kd2);
         r = r > (T)P.rlim ? (T)P.rlim : r;
     } else {
         Pr = 0;
@@ -333,9 +354,10 @@ __device__ __forceinline__ T sa_rhs(const KP &P, T nt0, const T *ntm, const T *n
     T g2 = gg * gg, g6 = g2 * g2 * g2;
     T c3 = (T)P.cw3, c6 = c3 * c3 * c3;
     c6 = c6 * c6;
-    T ratio = ((T)1 + c6) / (g6 + c6);
-    T fw = gg * sqrt(cbrt(ratio));
-    T Ds = (T)P.cw1 * fw * (nt0 / d) * (nt0 / d);
+    T ratio = N::div((T)1 + c6, g6 + c6);
+    T fw = gg * N::root6(ratio);
+    const T ntd = N::div(nt0, d);
+    T Ds = (T)P.cw1 * fw * ntd * ntd;
     T diff = 0, grad2 = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -343,7 +365,7 @@ __device__ __forceinline__ T sa_rhs(const KP &P, T nt0, const T *ntm, const T *n
         T ga = (T)0.5 * (ntp[a] - ntm[a]);
         grad2 += ga * ga;
     }
-    return -conv + Pr - Ds + (diff + (T)P.cb2 * grad2) / (T)P.sigma;
+    return -conv + Pr - Ds + N::div(diff + (T)P.cb2 * grad2, (T)P.sigma);
 }
 
 // ---------------------------------------------------------------------------
@@ -471,8 +493,8 @@ __host__ __device__ __forceinline__ void cm_collide(T *f, T drho, T rho, const T
 
 template <typename T> __device__ __forceinline__ T nut_of(const KP &P, T nt)
 {
-    T chi = nt / (T)P.nu, chi3 = chi * chi * chi;
-    return nt * chi3 / (chi3 + (T)(P.cv1 * P.cv1 * P.cv1));
+    T chi = Num<T>::div(nt, (T)P.nu), chi3 = chi * chi * chi;
+    return Num<T>::div(nt * chi3, chi3 + (T)(P.cv1 * P.cv1 * P.cv1));
 }
 
 // distance to the closest wall of a cell centre (Sec. 2.2)
