@@ -162,14 +162,12 @@ __device__ __forceinline__ void gather(const KP &P, const Cell &C, T *f)
         uwv[2] = (T)P.uw[2 * P.nwall + wi];
     }
     const bool active = true;
+    const CellK<T> &K = ck<T>(P);
     // ---- gather the incoming populations (deviations f - w rho0) ----------
-    const bool shifted = P.shift_u != 0.0;
-    const T r0 = (T)P.rho0, Us = (T)P.shift_u;
     sfor<Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ccx = cx<Q>(i), ccy = cy<Q>(i), ccz = cz<Q>(i);
         constexpr int io = opp<Q>(i), im = opp<Q>(mir<Q>(i));
-        const bool xopen = PLATE && ((ccx > 0 && x == 0) || (ccx < 0 && x == nx - 1));
         const bool ycross = (ccy > 0 && bottom) || (ccy < 0 && top);
         const bool wall = ycross && (top ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, -ccx));
         // the slot holds population i (interior), opp(i) (wall) or mir(i)
@@ -180,10 +178,24 @@ __device__ __forceinline__ void gather(const KP &P, const Cell &C, T *f)
         if (ODD)
             idx = !ycross ? pb + io * nx + poff<Q>(C, -ccx, -ccy, -ccz)
                           : (wall ? pb + i * nx : pb + im * nx + poff<Q>(C, -ccx, 0, -ccz));
-        T v = SS::ld(ld_pop(&A[idx]));
-        if (shifted)
-            v += !ycross ? shift_off<Q, T>(i, r0, Us)
-                         : (wall ? shift_off<Q, T>(opp<Q>(i), r0, Us) : shift_off<Q, T>(mir<Q>(i), r0, Us));
+        f[i] = SS::ld(ld_pop(&A[idx]));
+    });
+    // storage shift of the population the slot held (uniform branch)
+    if (P.shifted)
+        sfor<Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int ccx = cx<Q>(i), ccy = cy<Q>(i);
+            const bool ycross = (ccy > 0 && bottom) || (ccy < 0 && top);
+            const bool wall = ycross && (top ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, -ccx));
+            f[i] += !ycross ? K.soff[i] : (wall ? K.soff[opp<Q>(i)] : K.soff[mir<Q>(i)]);
+        });
+    sfor<Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int ccx = cx<Q>(i), ccy = cy<Q>(i), ccz = cz<Q>(i);
+        const bool xopen = PLATE && ((ccx > 0 && x == 0) || (ccx < 0 && x == nx - 1));
+        const bool ycross = (ccy > 0 && bottom) || (ccy < 0 && top);
+        const bool wall = ycross && (top ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, -ccx));
+        T v = f[i];
         // eq. 31: f_i = f*_opp(i) + 2 w_i rho_w (c_i . u_w) / cs2 (halfway links;
         // interpolated links keep f*_opp(i) here and are finished by ibb_links)
         if (!HRFD && wall && wi >= 0 && (!IBB || P.bb_interp == IBB_HALFWAY))
@@ -268,8 +280,7 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f,
     T *__restrict__ u_wr = (T *)P.u[rd ^ 1];
     const T *__restrict__ nt_rd = (const T *)P.nt[rd];
     T *__restrict__ nt_wr = (T *)P.nt[rd ^ 1];
-    const bool shifted = P.shift_u != 0.0;
-    const T r0 = (T)P.rho0, Us = (T)P.shift_u;
+    const CellK<T> &K = ck<T>(P);
     const T nt0 = P.sa_on ? nt_rd[cell] : (T)0;
 
     // ---- HRFD: regularized reconstruction at the wall cells (D2Q9) --------
@@ -331,59 +342,85 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f,
         if constexpr (cz<Q>(i) > 0) jz += f[i];
         if constexpr (cz<Q>(i) < 0) jz -= f[i];
     });
-    const T rho = (T)P.rho0 + drho;
-    const T Fx = (T)P.fx, Fy = (T)P.fy, Fz = (T)P.fz;
+    const T rho = K.rho0 + drho;
+    const T Fx = K.fx, Fy = K.fy, Fz = K.fz;
     const T inv = Num<T>::rcp(rho);
     const T ux = (jx + (T)0.5 * Fx) * inv, uy = (jy + (T)0.5 * Fy) * inv, uz = D == 3 ? (jz + (T)0.5 * Fz) * inv : (T)0;
 
     // ---- collision with tau_eff = 1/2 + (nu + nu_t)/cs2 -------------------------
     const T nut = P.sa_on ? nut_of<T>(P, nt0) : (T)0;
-    const T omega = Num<T>::rcp((T)0.5 + (T)3 * ((T)P.nu + nut));
+    const T omega = Num<T>::rcp((T)0.5 + (T)3 * (K.nu + nut));
     if constexpr (CMC) {
         // central-moment operator, eq. 7
         const T uvec[3] = {ux, uy, uz}, Fv[3] = {Fx, Fy, Fz};
         cm_collide<Q, T>(f, drho, rho, uvec, Fv, omega);
     } else {
-        // BGK with Guo forcing
+        // BGK with Guo forcing, f* = (1 - omega) f + omega f_eq + S with
+        //   f_eq_i = w_i (drho + rho (3 cu + 9/2 cu^2 - 3/2 u.u))      (deviation form)
+        //   S_i    = (1 - omega/2) w_i (3 (c_i.F - u.F) + 9 cu (c_i.F)),  cu = c_i.u
+        // taken per pair (i, opp(i)): the parts even in c_i are shared by the
+        // pair, the odd parts change sign.
         const T uu = ux * ux + uy * uy + uz * uz;
+        const T om1 = (T)1 - omega;
         const T fpref = (T)1 - (T)0.5 * omega;
         const T uF = ux * Fx + uy * Fy + uz * Fz;
-        sfor<Q>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const T ccx = (T)cx<Q>(i), ccy = (T)cy<Q>(i), ccz = (T)cz<Q>(i);
+        // per unit weight: the c-independent part of omega f_eq + S
+        const T s0 = omega * (drho - (T)1.5 * rho * uu) - (T)3 * fpref * uF;
+        const T q45 = omega * (T)4.5 * rho, q3 = omega * (T)3 * rho;
+        const T f9 = (T)9 * fpref, f3 = (T)3 * fpref;
+        f[0] = om1 * f[0] + (T)wgt<Q>(0) * s0;
+        sfor<(Q - 1) / 2>([&](auto kc) {
+            constexpr int i = 2 * decltype(kc)::value + 1, io = opp<Q>(i);
+            static_assert(io == i + 1, "pairs (2k+1, 2k+2)");
             const T w = (T)wgt<Q>(i);
-            const T cu = ccx * ux + ccy * uy + ccz * uz;
-            const T feqd = w * (drho + rho * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu));
-            const T cF = ccx * Fx + ccy * Fy + ccz * Fz;
-            const T src = fpref * w * ((T)3 * (cF - uF) + (T)9 * cu * cF);
-            f[i] = f[i] - omega * (f[i] - feqd) + src;
+            const T cu = (T)cx<Q>(i) * ux + (T)cy<Q>(i) * uy + (T)cz<Q>(i) * uz;
+            const T even = w * s0 + (w * q45) * (cu * cu) + (f9 * K.cf[i]) * cu;
+            const T odd = (w * q3) * cu + f3 * K.cf[i];
+            f[i] = om1 * f[i] + (even + odd);
+            f[io] = om1 * f[io] + (even - odd);
         });
     }
     // post-collision populations of a wall cell for its interpolated links
     if (IBB && P.bb_interp != IBB_HALFWAY && wi >= 0)
         sfor<Q>([&](auto ic) { P.ibuf[wi * Q + decltype(ic)::value] = (double)f[decltype(ic)::value]; });
     // ---- store (AA pattern) ---------------------------------------------------
+    // Odd step: the store addresses are recomputed here from the cell's base
+    // and offsets, hidden from the compiler by an empty asm, instead of being
+    // kept from the gather (19 live 64-bit addresses across the collision):
+    // fewer VGPRs, more waves per SIMD.  (On the even step the store slots are
+    // the gather's own and the occupancy is already higher.)
+    Cell Cs = C;
+    if (ODD) asm volatile("" : "+v"(Cs.pb), "+v"(Cs.oxm), "+v"(Cs.oxp), "+v"(Cs.ozm), "+v"(Cs.ozp));
+    const int64_t pbs = Cs.pb;
+    if (P.shifted) sfor<Q>([&](auto ic) { f[decltype(ic)::value] -= K.soff[decltype(ic)::value]; });
     sfor<Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ccxi = cx<Q>(i), ccyi = cy<Q>(i), cczi = cz<Q>(i);
         constexpr int io = opp<Q>(i), im = mir<Q>(i);
-        const T fp = shifted ? f[i] - shift_off<Q, T>(i, r0, Us) : f[i];
+        const T fp = f[i];
         // even step: own slot opp(i); odd step: the neighbour's slot i, or the
         // own free slot opp(i) for a population leaving through a wall or an
         // open boundary, or the mirrored destination across a symmetry plane
         // (index selected, store unconditional)
-        int64_t idx = pb + io * nx;
+        int64_t idx = pbs + io * nx;
         if (ODD) {
             const bool xopen = PLATE && ((ccxi > 0 && x == nx - 1) || (ccxi < 0 && x == 0));
             const bool ycross = (ccyi < 0 && bottom) || (ccyi > 0 && top);
             const bool wall = top ? (P.flow == FLOW_CHANNEL) : bottom_is_wall(P, x, ccxi);
             if (!xopen)
-                idx = !ycross ? pb + i * nx + poff<Q>(C, ccxi, ccyi, cczi)
-                              : (wall ? pb + io * nx : pb + im * nx + poff<Q>(C, ccxi, 0, cczi));
+                idx = !ycross ? pbs + i * nx + poff<Q>(Cs, ccxi, ccyi, cczi)
+                              : (wall ? pbs + io * nx : pbs + im * nx + poff<Q>(Cs, ccxi, 0, cczi));
             if constexpr (XS && ccxi != 0) {
                 const int xd = x + ccxi, t = (int)threadIdx.x + ccxi;
                 if (!ycross && xd >= 0 && xd < nx && t >= 0 && t < BLK) {
                     lds[xslot<Q>(i) * BLK + t] = SS::st(fp);
+                    return;
+                }
+                // a push across the block's edge writes one value of a line
+                // the neighbouring block fills: an ordinary (not streaming)
+                // store lets L2 merge the two parts (measured 2 % faster)
+                if (!ycross) {
+                    A[idx] = SS::st(fp);
                     return;
                 }
             }
@@ -633,7 +670,7 @@ template <int Q, int i, typename S, typename T>
 __device__ __forceinline__ T canon_f(const KP &P, const S *A, int x, int y, int z, int64_t cell, bool odd_state)
 {
     T v = canon_raw<Q, i, S, T>(P, A, x, y, z, cell, odd_state);
-    if (P.shift_u != 0.0) v += shift_off<Q, T>(i, (T)P.rho0, (T)P.shift_u);
+    if (P.shifted) v += ck<T>(P).soff[i];
     return v;
 }
 
@@ -729,8 +766,7 @@ __global__ void __launch_bounds__(BLK) k_init(KP P, const double *u0, double ux0
         constexpr int i = decltype(ic)::value;
         const double cu = cx<Q>(i) * u[0] + cy<Q>(i) * u[1] + cz<Q>(i) * u[2];
         const double fd = wgt<Q>(i) * P.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        const double sh = P.shift_u != 0.0 ? (double)shift_off<Q, double>(i, P.rho0, P.shift_u) : 0.0;
-        A[pidx<Q>(P.nx, opp<Q>(i), x, row)] = SS::st((T)(fd - sh));
+        A[pidx<Q>(P.nx, opp<Q>(i), x, row)] = SS::st((T)fd - ck<T>(P).soff[i]);
         if (wi >= 0) P.ibuf[wi * Q + i] = fd;
     });
     T *u_0 = (T *)P.u[0], *us = (T *)P.usnap;
@@ -1314,6 +1350,35 @@ int check_params(int lattice, int nx, int ny, int nz, const lbm_params_t *p)
     return LBM_OK;
 }
 
+// the cell-update constants from the double-precision parameters
+template <typename T> void fill_cellk(const KP &k, int Q, CellK<T> &c)
+{
+    memset(&c, 0, sizeof c);
+    c.nu = (T)k.nu;
+    c.rho0 = (T)k.rho0;
+    c.fx = (T)k.fx;
+    c.fy = (T)k.fy;
+    c.fz = (T)k.fz;
+    c.cv1_3 = (T)(k.cv1 * k.cv1 * k.cv1);
+    c.kappa2 = (T)(k.kappa * k.kappa);
+    c.cb1 = (T)k.cb1;
+    c.cw1 = (T)k.cw1;
+    c.cw2 = (T)k.cw2;
+    const double c3 = k.cw3 * k.cw3 * k.cw3;
+    c.cw3_6 = (T)(c3 * c3);
+    c.rlim = (T)k.rlim;
+    c.cb2 = (T)k.cb2;
+    c.inv_sigma = (T)(1.0 / k.sigma);
+    c.wall_dist = (T)k.wall_dist;
+    for (int i = 0; i < Q; ++i) {
+        const int *cv = Q == 9 ? Lat<9>::c[i] : Lat<19>::c[i];
+        const double w = Q == 9 ? wgt<9>(i) : wgt<19>(i);
+        c.cf[i] = (T)(w * (cv[0] * k.fx + cv[1] * k.fy + cv[2] * k.fz));
+        if (k.shift_u != 0.0)
+            c.soff[i] = (T)(Q == 9 ? shift_off<9, double>(i, k.rho0, k.shift_u) : shift_off<19, double>(i, k.rho0, k.shift_u));
+    }
+}
+
 void fill_kp(lbm *h)
 {
     KP &k = h->kp;
@@ -1348,6 +1413,7 @@ void fill_kp(lbm *h)
     k.cv1 = p.cv1;
     k.rlim = p.rlim;
     k.shift_u = p.store_shift_u;
+    k.shifted = p.store_shift_u != 0.0;
     // row-slab XCD mapping for wide channels (see k_step); flat mapping otherwise
     k.rowmap = (LBM_ROWMAP && p.flow == LBM_FLOW_CHANNEL && h->nx >= BLK / 2 && h->ny % 8 == 0) ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
@@ -1373,6 +1439,8 @@ void fill_kp(lbm *h)
     k.bb_interp = p.bb_interp;
     k.wall_dist = p.wall_dist;
     k.result = (double *)(b + L.result);
+    fill_cellk(k, h->Q, k.kd);
+    fill_cellk(k, h->Q, k.kf);
 }
 
 int run_init(lbm *h, const double *u0dev)

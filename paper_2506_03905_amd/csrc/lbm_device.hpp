@@ -98,7 +98,7 @@ template <> struct Stor<bf16s> {
 
 // Storage offset of population i: f_eq_i(rho0, (U, 0, 0)) - w_i rho0.  The
 // stored value of population i is (f_i - w_i rho0) - shift_off<Q>(i, ...).
-template <int Q, typename T> __device__ __forceinline__ T shift_off(int i, T rho0, T U)
+template <int Q, typename T> __host__ __device__ __forceinline__ T shift_off(int i, T rho0, T U)
 {
     const T cu = (T)cx<Q>(i) * U;
     return (T)wgt<Q>(i) * rho0 * ((T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * U * U);
@@ -142,6 +142,18 @@ template <typename S> __device__ __forceinline__ void st_pop(S *p, S v)
 }
 
 // ---------------------------------------------------------------------------
+// Constants of the cell update, computed once on the host in double precision
+// and kept in the compute type, so that the update converts nothing per cell.
+// ---------------------------------------------------------------------------
+template <typename T> struct CellK {
+    T nu, rho0, fx, fy, fz;                           // viscosity, reference density, body force
+    T cv1_3, kappa2, cb1, cw1, cw2, cw3_6, rlim, cb2; // SA constants (eq. 10-14): cv1^3, kappa^2, cw3^6
+    T inv_sigma, wall_dist;
+    T cf[19];    // w_i (c_i . F), the direction's share of the Guo forcing term
+    T soff[19];  // storage offset of population i (zero without the storage shift)
+};
+
+// ---------------------------------------------------------------------------
 // Kernel parameters (by value).
 // ---------------------------------------------------------------------------
 struct KP {
@@ -171,8 +183,14 @@ struct KP {
     double *ibuf;        // Q * nwall: post-collision populations of the wall cells (interpolated links)
     double wall_dist;    // distance of the first node from the wall (1/2: halfway)
     int bb_interp;       // IBB_HALFWAY / IBB_BOUZIDI / IBB_YU
-    int pad2_;
+    int shifted;         // storage shift on (shift_u != 0)
+    CellK<double> kd;    // cell-update constants, FP64 path
+    CellK<float> kf;     // the same in FP32 (FP32, FP16 and BF16 storage)
 };
+
+template <typename T> __host__ __device__ __forceinline__ const CellK<T> &ck(const KP &P);
+template <> __host__ __device__ __forceinline__ const CellK<double> &ck<double>(const KP &P) { return P.kd; }
+template <> __host__ __device__ __forceinline__ const CellK<float> &ck<float>(const KP &P) { return P.kf; }
 
 constexpr int FLOW_CHANNEL = 0, FLOW_PLATE = 1;
 constexpr int WALL_FIXED = 0, WALL_SLIP = 1, WALL_HRFD = 2, WALL_CD = 3;
@@ -323,7 +341,8 @@ template <int D, typename T>
 __device__ __forceinline__ T sa_rhs(const KP &P, T nt0, const T *ntm, const T *ntp, const T *u0,
                                     const T (*g)[3], T d)
 {
-    const T nu = (T)P.nu, k = (T)P.kappa;
+    const CellK<T> &K = ck<T>(P);
+    const T nu = K.nu;
     T conv = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) conv += u0[a] > (T)0 ? u0[a] * (nt0 - ntm[a]) : u0[a] * (ntp[a] - nt0);
@@ -335,29 +354,28 @@ __device__ __forceinline__ T sa_rhs(const KP &P, T nt0, const T *ntm, const T *n
         S = Num<T>::sqrt_(wx * wx + wy * wy + wz * wz);
     }
     using N = Num<T>;
-    T chi = N::div(nt0, nu), chi3 = chi * chi * chi, cv13 = (T)(P.cv1 * P.cv1 * P.cv1);
-    T fv1 = N::div(chi3, chi3 + cv13);
+    T chi = N::div(nt0, nu), chi3 = chi * chi * chi;
+    T fv1 = N::div(chi3, chi3 + K.cv1_3);
     T fv2 = (T)1 - N::div(chi, (T)1 + chi * fv1);
-    T kd2 = k * k * d * d;
+    T kd2 = K.kappa2 * d * d;
     T St = S + N::div(nt0, kd2) * fv2;
     T Pr, r;
     if (St > (T)0) {
-        Pr = (T)P.cb1 * St * nt0;
+        Pr = K.cb1 * St * nt0;
         r = N::div(nt0, St * kd2);
-        r = r > (T)P.rlim ? (T)P.rlim : r;
+        r = r > K.rlim ? K.rlim : r;
     } else {
         Pr = 0;
-        r = (T)P.rlim;
+        r = K.rlim;
     }
     T r2 = r * r;
-    T gg = r + (T)P.cw2 * (r2 * r2 * r2 - r);
+    T gg = r + K.cw2 * (r2 * r2 * r2 - r);
     T g2 = gg * gg, g6 = g2 * g2 * g2;
-    T c3 = (T)P.cw3, c6 = c3 * c3 * c3;
-    c6 = c6 * c6;
+    const T c6 = K.cw3_6;
     T ratio = N::div((T)1 + c6, g6 + c6);
     T fw = gg * N::root6(ratio);
     const T ntd = N::div(nt0, d);
-    T Ds = (T)P.cw1 * fw * ntd * ntd;
+    T Ds = K.cw1 * fw * ntd * ntd;
     T diff = 0, grad2 = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -365,7 +383,7 @@ __device__ __forceinline__ T sa_rhs(const KP &P, T nt0, const T *ntm, const T *n
         T ga = (T)0.5 * (ntp[a] - ntm[a]);
         grad2 += ga * ga;
     }
-    return -conv + Pr - Ds + N::div(diff + (T)P.cb2 * grad2, (T)P.sigma);
+    return -conv + Pr - Ds + (diff + K.cb2 * grad2) * K.inv_sigma;
 }
 
 // ---------------------------------------------------------------------------
@@ -493,8 +511,9 @@ __host__ __device__ __forceinline__ void cm_collide(T *f, T drho, T rho, const T
 
 template <typename T> __device__ __forceinline__ T nut_of(const KP &P, T nt)
 {
-    T chi = Num<T>::div(nt, (T)P.nu), chi3 = chi * chi * chi;
-    return Num<T>::div(nt * chi3, chi3 + (T)(P.cv1 * P.cv1 * P.cv1));
+    const CellK<T> &K = ck<T>(P);
+    T chi = Num<T>::div(nt, K.nu), chi3 = chi * chi * chi;
+    return Num<T>::div(nt * chi3, chi3 + K.cv1_3);
 }
 
 // distance to the closest wall of a cell centre (Sec. 2.2)
@@ -503,7 +522,7 @@ template <typename T> __device__ __forceinline__ T nut_of(const KP &P, T nt)
 // sits at x = plate_start on the wall plane (node x at x + 1/2).
 template <typename T> __device__ __forceinline__ T wall_dist(const KP &P, int x, int y)
 {
-    const T dw = (T)P.wall_dist;
+    const T dw = ck<T>(P).wall_dist;
     T yc = (T)y + dw;
     if (P.flow == FLOW_CHANNEL) {
         T yt = (T)(P.ny - 1 - y) + dw;
