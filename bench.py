@@ -304,6 +304,11 @@ def main():
                      "kernel": "k_step", "bytes_per_lup": bpl,
                      "algorithmic_bytes_per_launch": bpl * ncell,
                      "kernel_ms": round(k_ms, 4),
+                     # HBM bytes the counters measured per launch over the launch time
+                     "measured_gbs": None if traffic is None else round(traffic / (k_ms * 1e-3) / 1e9, 1),
+                     # the populations alone (read and written once), the figure LBM codes quote
+                     "pops_only_gbs": round(2 * 19 * {"f64": 8, "f32": 4}.get(args.precision, 2) * ncell
+                                            / (k_ms * 1e-3) / 1e9, 1),
                      "wall_kernel_ms": round(tm["wall_ms"] / max(tm["wall_launches"], 1), 4)},
         "residual": {"l2_du_rel": res["l2_du_rel"], "mean_u_tau": res["mean_u_tau"],
                      "nan_flag": res["nan_flag"]},
