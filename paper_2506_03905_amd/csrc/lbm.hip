@@ -2,15 +2,21 @@
 //
 // One time step (Ponsin & Lozano, arXiv 2506.03905) is two launches:
 //   k_step  fused streaming (single-buffer AA pattern) + wall links
-//           (bounce-back eq. 31 with the wall velocity of eq. 35, or the
-//           regularized reconstruction eq. 19/23/26-28) + plate edges +
-//           moments (eq. 4-5) + BGK/Guo collision with tau from nu + nu_t
-//           (eq. 8, 10) + the Spalart-Allmaras update (eq. 11-14);
+//           (halfway bounce-back eq. 31 with the wall velocity of eq. 35,
+//           Bouzidi's or Yu's interpolated rules eq. 36-37, or the
+//           regularized reconstruction eq. 19/23/26-28 with the gradient of
+//           eq. 27-28 or of Cai-Degrigny, eq. 29-30) + plate edges +
+//           moments (eq. 4-5) + BGK/Guo or central-moment (eq. 7) collision
+//           with tau from nu + nu_t (eq. 8, 10) + the Spalart-Allmaras
+//           update (eq. 11-14);
 //   k_wall  the per-wall-cell FP64 Newton solve for u_tau at the reference
 //           node F (Sec. 3.1, eq. 20-22), the slip velocity (eq. 35) and the
 //           SA Dirichlet value nu_tilde_B = nu kappa y_B+ (Sec. 2.2).
 // A residual reduction (mass, momentum, velocity change, mean u_tau) runs
-// every K steps in FP64 with a fixed summation order.
+// every K steps in FP64 with a fixed summation order.  The serving pool runs
+// the same cell update for many lattices at once: small ones in a persistent
+// kernel with the time loop inside (k_serve), large ones in shared launches
+// per phase (k_mstep, k_mwall, k_mreduce).
 //
 // AA pattern: after an even step (and after initialisation) slot A[opp(i)][x]
 // holds the post-collision f*_i(x); an odd step pulls from neighbours and

@@ -13,8 +13,9 @@
 
 The traffic summary ends with a JSON block (fields ``fetch_bytes``,
 ``write_bytes``, ``traffic_bytes``, ``source_sha256``) that ``bench.py``
-reads; ``source_sha256`` is the hash of the kernel sources the counters were
-taken with, so a later change of the kernels voids the figure.
+reads; ``source_sha256`` is the hash of the kernel sources' code (comments and
+spacing left out) the counters were taken with, so a later change of the
+kernels voids the figure.
 """
 from __future__ import annotations
 
@@ -31,11 +32,36 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/lbm.hip", "csrc/lbm_device.hpp")
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank space, so that an edit of a
+    comment does not void the recorded counters (string literals are kept)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"':
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_sha256() -> str:
+    """Hash of the kernel sources' code (comments and spacing excluded)."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, rel), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()
 
 
