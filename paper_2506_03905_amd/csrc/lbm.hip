@@ -1216,8 +1216,12 @@ struct lbm {
     int reduce_count;
     bool diverged;
     bool timing;
-    std::vector<hipEvent_t> ev_step, ev_wall;  // pairs
-    size_t n_step_ev, n_wall_ev;
+    // One chain of events on the stream; the interval that ends at event k
+    // belongs to ev_kind[k] (a k_step or k_wall launch, or nothing timed).
+    // One event per launch keeps the instrumentation light.
+    std::vector<hipEvent_t> ev;
+    std::vector<char> ev_kind;
+    size_t n_ev;
     double acc_step_ms, acc_wall_ms;
     int64_t acc_step_n, acc_wall_n;
 };
@@ -1459,35 +1463,40 @@ int run_init(lbm *h, const double *u0dev)
     return LBM_DISPATCH(h, init, h, u0dev);
 }
 
-int record(lbm *h, std::vector<hipEvent_t> &v, size_t &n)
+// mark the end of an interval of the given kind on the handle's stream
+enum : char { EV_NONE = 0, EV_STEP = 1, EV_WALL = 2 };
+
+int record(lbm *h, char kind)
 {
-    if (n >= v.size()) {
+    if (h->n_ev >= h->ev.size()) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
-        v.push_back(e);
+        h->ev.push_back(e);
+        h->ev_kind.push_back(EV_NONE);
     }
-    HIPCHK(hipEventRecord(v[n], h->stream));
-    ++n;
+    HIPCHK(hipEventRecord(h->ev[h->n_ev], h->stream));
+    h->ev_kind[h->n_ev] = kind;
+    ++h->n_ev;
     return LBM_OK;
 }
 
 int flush_timing(lbm *h)
 {
-    if (h->n_step_ev == 0 && h->n_wall_ev == 0) return LBM_OK;
+    if (h->n_ev == 0) return LBM_OK;
     HIPCHK(hipStreamSynchronize(h->stream));
-    for (size_t i = 0; i + 1 < h->n_step_ev; i += 2) {
+    for (size_t k = 1; k < h->n_ev; ++k) {
+        if (h->ev_kind[k] == EV_NONE) continue;
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, h->ev_step[i], h->ev_step[i + 1]));
-        h->acc_step_ms += ms;
-        h->acc_step_n++;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev[k - 1], h->ev[k]));
+        if (h->ev_kind[k] == EV_STEP) {
+            h->acc_step_ms += ms;
+            h->acc_step_n++;
+        } else {
+            h->acc_wall_ms += ms;
+            h->acc_wall_n++;
+        }
     }
-    for (size_t i = 0; i + 1 < h->n_wall_ev; i += 2) {
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, h->ev_wall[i], h->ev_wall[i + 1]));
-        h->acc_wall_ms += ms;
-        h->acc_wall_n++;
-    }
-    h->n_step_ev = h->n_wall_ev = 0;
+    h->n_ev = 0;
     return LBM_OK;
 }
 
@@ -1572,7 +1581,7 @@ int lbm_create(lbm_lattice_t lattice, int nx, int ny, int nz, const lbm_params_t
     h->bytes = buf_bytes;
     h->stream = (hipStream_t)stream;
     h->timing = false;
-    h->n_step_ev = h->n_wall_ev = 0;
+    h->n_ev = 0;
     h->acc_step_ms = h->acc_wall_ms = 0.0;
     h->acc_step_n = h->acc_wall_n = 0;
     fill_kp(h);
@@ -1630,27 +1639,30 @@ int lbm_step(lbm_t *h, int64_t n)
     if (!h) return fail(LBM_ESTATE, "NULL handle");
     if (n < 0) return fail(LBM_EINVAL, "negative step count");
     if (h->diverged) return fail(LBM_EDIVERGED, "the solution diverged at or before step %lld", (long long)h->last_reduce_step);
+    int rc;
+    // the first interval of this call starts here (host time before the call
+    // is not counted)
+    if (n > 0 && h->timing && (rc = record(h, EV_NONE))) return rc;
     for (int64_t s = 0; s < n; ++s) {
         const int64_t next = h->step + 1;
         const bool odd = (next & 1) != 0;
         const int rd = (int)(h->step & 1);
-        int rc;
-        if (h->timing && (rc = record(h, h->ev_step, h->n_step_ev))) return rc;
         rc = LBM_DISPATCH(h, step, h, odd, rd);
         if (rc) return rc;
-        if (h->timing && (rc = record(h, h->ev_step, h->n_step_ev))) return rc;
-        if (h->timing && (rc = record(h, h->ev_wall, h->n_wall_ev))) return rc;
+        if (h->timing && (rc = record(h, EV_STEP))) return rc;
         rc = LBM_DISPATCH(h, wall, h, rd ^ 1);
         if (rc) return rc;
-        if (h->timing && (rc = record(h, h->ev_wall, h->n_wall_ev))) return rc;
+        if (h->timing && (rc = record(h, EV_WALL))) return rc;
         h->step = next;
         if (h->p.reduce_every > 0 && h->step % h->p.reduce_every == 0) {
             rc = do_reduce(h);
             if (rc) return rc;
+            if (h->timing && (rc = record(h, EV_NONE))) return rc;
         }
-        if (h->timing && h->n_step_ev >= 4096) {
+        if (h->timing && h->n_ev >= 8192) {
             rc = flush_timing(h);
             if (rc) return rc;
+            if (s + 1 < n && (rc = record(h, EV_NONE))) return rc;
         }
     }
     return LBM_OK;
@@ -1835,8 +1847,7 @@ int lbm_destroy(lbm_t *h)
 {
     if (!h) return fail(LBM_ESTATE, "NULL handle");
     (void)hipStreamSynchronize(h->stream);
-    for (hipEvent_t e : h->ev_step) (void)hipEventDestroy(e);
-    for (hipEvent_t e : h->ev_wall) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     delete h;
     return LBM_OK;
 }
