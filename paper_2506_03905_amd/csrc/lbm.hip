@@ -266,26 +266,76 @@ template <typename T> __device__ __forceinline__ void zou_he(const KP &P, T *f)
 }
 
 // ---------------------------------------------------------------------------
+// Spalart-Allmaras update of one cell (eq. 10-14) from nu_tilde^n and
+// u^{n-1} (ping-pong index rd); wall cells get their value from k_wall.
+// ---------------------------------------------------------------------------
+template <int Q, typename T, bool PLATE>
+__device__ __forceinline__ void sa_cell(const KP &P, const Cell &C, int rd, T nt0)
+{
+    constexpr int D = Lat<Q>::D;
+    if (!P.sa_on) return;
+    const int ny = P.ny;
+    const int64_t N = P.ncell;
+    const int x = C.x, y = C.y;
+    const int64_t cell = C.cell, wi = C.wi, sy = C.sy;
+    const int64_t oxm = C.oxm, oxp = C.oxp, ozm = C.ozm, ozp = C.ozp;
+    const T *__restrict__ u_rd = (const T *)P.u[rd];
+    const T *__restrict__ nt_rd = (const T *)P.nt[rd];
+    T *__restrict__ nt_wr = (T *)P.nt[rd ^ 1];
+    const bool dirichlet = (wi >= 0) || (PLATE && x == 0);
+    if (dirichlet) {
+        if (wi < 0) nt_wr[cell] = nt0;  // plate inlet keeps its value; walls: k_wall
+        return;
+    }
+    T ntm[3], ntp[3], g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    // x neighbours (plate outlet: zero-gradient copy)
+    {
+        const int64_t cm = cell + oxm, cp = cell + oxp;  // plate: oxp = 0 at the outlet
+        ntm[0] = nt_rd[cm];
+        ntp[0] = nt_rd[cp];
+        g[1][0] = (u_rd[N + cp] - u_rd[N + cm]) * (T)0.5;
+        if (D == 3) g[2][0] = (u_rd[2 * N + cp] - u_rd[2 * N + cm]) * (T)0.5;
+    }
+    // y neighbours (plate symmetry planes: mirror image, same tangential velocity)
+    {
+        const int64_t cm = (y == 0) ? cell : cell - sy, cp = (y == ny - 1) ? cell : cell + sy;
+        ntm[1] = nt_rd[cm];
+        ntp[1] = nt_rd[cp];
+        g[0][1] = (u_rd[cp] - u_rd[cm]) * (T)0.5;
+        if (D == 3) g[2][1] = (u_rd[2 * N + cp] - u_rd[2 * N + cm]) * (T)0.5;
+    }
+    if (D == 3) {
+        const int64_t cm = cell + ozm, cp = cell + ozp;
+        ntm[2] = nt_rd[cm];
+        ntp[2] = nt_rd[cp];
+        g[0][2] = (u_rd[cp] - u_rd[cm]) * (T)0.5;
+        g[1][2] = (u_rd[N + cp] - u_rd[N + cm]) * (T)0.5;
+    }
+    T u0[3] = {u_rd[cell], u_rd[N + cell], D == 3 ? u_rd[2 * N + cell] : (T)0};
+    const T d = wall_dist<T>(P, x, y);
+    const T rhs = sa_rhs<D, T>(P, nt0, ntm, ntp, u0, g, d);
+    nt_wr[cell] = clamp0(nt0 + rhs);
+}
+
+// ---------------------------------------------------------------------------
 // finish: HRFD reconstruction (wall cells), moments, collision, AA store,
 // velocity, wall density and the Spalart-Allmaras update of one cell.
 // rd: ping-pong index of u^{n-1} / nu_tilde^n; results go to rd ^ 1.
 // ---------------------------------------------------------------------------
 template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false, bool IBB = false>
-__device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f, S *lds = nullptr)
+__device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S *lds = nullptr)
 {
     constexpr int D = Lat<Q>::D;
     using SS = Stor<S>;
-    const int nx = P.nx, ny = P.ny;
+    const int nx = P.nx;
     const int64_t N = P.ncell;
     const int x = C.x, y = C.y, z = C.z;
     const bool bottom = C.bottom, top = C.top;
-    const int64_t cell = C.cell, wi = C.wi, sy = C.sy, pb = C.pb;
-    const int64_t oxm = C.oxm, oxp = C.oxp, ozm = C.ozm, ozp = C.ozp;
+    const int64_t cell = C.cell, wi = C.wi, sy = C.sy;
     S *__restrict__ A = (S *)P.pops;
     const T *__restrict__ u_rd = (const T *)P.u[rd];
     T *__restrict__ u_wr = (T *)P.u[rd ^ 1];
     const T *__restrict__ nt_rd = (const T *)P.nt[rd];
-    T *__restrict__ nt_wr = (T *)P.nt[rd ^ 1];
     const CellK<T> &K = ck<T>(P);
     const T nt0 = P.sa_on ? nt_rd[cell] : (T)0;
 
@@ -439,43 +489,9 @@ __device__ __forceinline__ void finish(const KP &P, const Cell &C, int rd, T *f,
     if (wi >= 0) P.wrho[wi] = (double)rho;
 
     // ---- Spalart-Allmaras update from nu_tilde^n and u^{n-1} -------------------
-    auto sa_update = [&]() {
-    if (!P.sa_on) return;
-    const bool dirichlet = (wi >= 0) || (PLATE && x == 0);
-    if (dirichlet) {
-        if (wi < 0) nt_wr[cell] = nt0;  // plate inlet keeps its value; walls: k_wall
-        return;
-    }
-    T ntm[3], ntp[3], g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    // x neighbours (plate outlet: zero-gradient copy)
-    {
-        const int64_t cm = cell + oxm, cp = cell + oxp;  // plate: oxp = 0 at the outlet
-        ntm[0] = nt_rd[cm];
-        ntp[0] = nt_rd[cp];
-        g[1][0] = (u_rd[N + cp] - u_rd[N + cm]) * (T)0.5;
-        if (D == 3) g[2][0] = (u_rd[2 * N + cp] - u_rd[2 * N + cm]) * (T)0.5;
-    }
-    // y neighbours (plate symmetry planes: mirror image, same tangential velocity)
-    {
-        const int64_t cm = (y == 0) ? cell : cell - sy, cp = (y == ny - 1) ? cell : cell + sy;
-        ntm[1] = nt_rd[cm];
-        ntp[1] = nt_rd[cp];
-        g[0][1] = (u_rd[cp] - u_rd[cm]) * (T)0.5;
-        if (D == 3) g[2][1] = (u_rd[2 * N + cp] - u_rd[2 * N + cm]) * (T)0.5;
-    }
-    if (D == 3) {
-        const int64_t cm = cell + ozm, cp = cell + ozp;
-        ntm[2] = nt_rd[cm];
-        ntp[2] = nt_rd[cp];
-        g[0][2] = (u_rd[cp] - u_rd[cm]) * (T)0.5;
-        g[1][2] = (u_rd[N + cp] - u_rd[N + cm]) * (T)0.5;
-    }
-    T u0[3] = {u_rd[cell], u_rd[N + cell], D == 3 ? u_rd[2 * N + cell] : (T)0};
-    const T d = wall_dist<T>(P, x, y);
-    const T rhs = sa_rhs<D, T>(P, nt0, ntm, ntp, u0, g, d);
-    nt_wr[cell] = clamp0(nt0 + rhs);
-    };
-    sa_update();
+    // (the staged odd step runs it after its staged stores: cell_update)
+    if (!XS) sa_cell<Q, T, PLATE>(P, C, rd, nt0);
+    return nt0;
 }
 
 // ---------------------------------------------------------------------------
@@ -495,10 +511,11 @@ __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, i
         // a block covers columns [x - tid, x - tid + BLK) of one row
         __shared__ S lds[nxdirs<Q>() * BLK];
         T f[Q];
+        T nt0 = 0;
         if (active) {
             gather<Q, S, T, ODD, PLATE, HRFD, IBB>(P, C, f);
             if constexpr (IBB && !HRFD) ibb_links<Q, T, false>(P, C, f);
-            finish<Q, S, T, ODD, PLATE, HRFD, CMC, true, IBB>(P, C, rd, f, lds);
+            nt0 = finish<Q, S, T, ODD, PLATE, HRFD, CMC, true, IBB>(P, C, rd, f, lds);
         }
         __syncthreads();
         S *__restrict__ A = (S *)P.pops;
@@ -512,6 +529,9 @@ __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, i
                     st_pop(&A[C.pb + i * nx + poff<Q>(C, 0, ccy, ccz)], lds[xslot<Q>(i) * BLK + tid]);
             }
         });
+        // the SA update after the staged stores: they leave the block sooner
+        // (odd step 2 % faster than with the update before the barrier)
+        if (active) sa_cell<Q, T, PLATE>(P, C, rd, nt0);
         return;
     }
     T f[Q];
