@@ -86,14 +86,8 @@ template <> struct Stor<_Float16> {
 };
 template <> struct Stor<bf16s> {
     __device__ static float ld(bf16s v) { return __uint_as_float(static_cast<uint32_t>(v.b) << 16); }
-    // round to nearest even (finite inputs; NaN stays NaN through the high bits)
-    __device__ static bf16s st(float v)
-    {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7f800000u) == 0x7f800000u) return bf16s{static_cast<uint16_t>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u))};
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return bf16s{static_cast<uint16_t>(u >> 16)};
-    }
+    // round to nearest even, NaN kept a NaN: one hardware conversion on gfx950
+    __device__ static bf16s st(float v) { return bf16s{__builtin_bit_cast(uint16_t, static_cast<__bf16>(v))}; }
 };
 
 // Storage offset of population i: f_eq_i(rho0, (U, 0, 0)) - w_i rho0.  The
