@@ -20,6 +20,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm_oracle.so")
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
+_HDR = os.path.join(_HERE, "lbm_oracle.h")
+# A different build of the oracle (the planted-mistake test loads mutated
+# copies through this variable; nothing else sets it).
+_LIB_OVERRIDE = os.environ.get("LBM_ORACLE_LIB")
 
 CHANNEL, PLATE = 0, 1
 BB_FIXED, BB_SLIP, HRFD, CAI_DEGRIGNY = 0, 1, 2, 3
@@ -28,14 +32,28 @@ BGK, CM = 0, 1
 IBB_HALFWAY, IBB_BOUZIDI, IBB_YU = 0, 1, 2
 
 
+def compile_oracle(src: str, out: str) -> str:
+    """gcc, no fast-math, no FMA contraction; OpenMP over lattice rows."""
+    tmp = out + ".tmp"
+    subprocess.check_call(
+        ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+         "-fopenmp", "-Wall", "-Wno-unused-function", "-I", _HERE, src, "-o", tmp, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
+def _stale() -> bool:
+    if not os.path.exists(LIB_PATH):
+        return True
+    t = os.path.getmtime(LIB_PATH)
+    return any(os.path.getmtime(f) > t for f in (_SRC, _HDR))
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(LIB_PATH):
-        tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-             "-fno-fast-math", "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, LIB_PATH)
+    """Compile the oracle (always with force=True; otherwise only when the
+    library is missing or older than its sources)."""
+    if force or _stale():
+        compile_oracle(_SRC, LIB_PATH)
     return LIB_PATH
 
 
@@ -83,10 +101,11 @@ _lib_handle = None
 def lib():
     global _lib_handle
     if _lib_handle is None:
-        if not os.path.exists(LIB_PATH):
-            build()
-        L = ctypes.CDLL(LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
+        if _LIB_OVERRIDE:
+            L = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            build(force=False)
+            L = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
         L.orc_create.restype = vp
         L.orc_create.argtypes = [ctypes.POINTER(Params), vp]
@@ -120,7 +139,8 @@ def lib():
             [ctypes.c_double] * 5
         L.orc_cai_degrigny_grad.restype = ctypes.c_double
         L.orc_cai_degrigny_grad.argtypes = [ctypes.c_int] + [ctypes.c_double] * 6
-        _ = dp
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_get_threads.restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
 
@@ -131,6 +151,15 @@ def _ptr(a: np.ndarray):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's row loops (results do not depend on them)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 # --- per-cell building blocks ------------------------------------------------

@@ -31,6 +31,30 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads: the per-cell loops are shared out by rows (OpenMP).  Every cell's
+ * arithmetic is the same whatever thread runs it, and no loop sums across
+ * cells, so any thread count gives bitwise the same result. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 #define CS2 (1.0 / 3.0)
 
@@ -436,6 +460,7 @@ static void wall_function(orc *o, double *nt_out)
 {
     const orc_params *p = &o->p;
     const double yB = p->wall_dist, yF = 1.0 + p->wall_dist; /* Sec. 3.1: B and F */
+#pragma omp parallel for schedule(static)
     for (int64_t w = 0; w < o->nwall; ++w) {
         double n[3] = {0.0, (double)o->wside[w], 0.0};
         double uF[3], uB[3];
@@ -587,6 +612,7 @@ static void interpolated_bounce_back(orc *o, int outlet)
     const int Q = p->q;
     const int64_t N = o->ncell;
     const double q = p->wall_dist;
+#pragma omp parallel for schedule(static)
     for (int64_t w = 0; w < o->nwall; ++w) {
         const int64_t cell = o->wB[w];
         const int side = o->wside[w];
@@ -627,6 +653,7 @@ static void stream(orc *o)
     const orc_params *p = &o->p;
     const int Q = p->q, nx = p->nx, ny = p->ny, nz = p->nz;
     const int64_t N = o->ncell;
+#pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -672,12 +699,14 @@ static void stream(orc *o)
     if (p->flow == ORC_PLATE) {
         /* outlet: the unknown populations are copied from the streamed
          * populations of the column x = nx - 2 */
+#pragma omp parallel for schedule(static)
         for (int y = 0; y < ny; ++y) {
             int64_t c1 = cidx(o, nx - 1, y, 0), c2 = cidx(o, nx - 2, y, 0);
             for (int i = 0; i < Q; ++i)
                 if (o->c[3 * i] < 0) o->fnew[i * N + c1] = o->fnew[i * N + c2];
         }
         /* inlet: Zou-He with u = (u_inlet, 0) */
+#pragma omp parallel for schedule(static)
         for (int y = 0; y < ny; ++y) {
             int64_t c0 = cidx(o, 0, y, 0);
             double f[9];
@@ -749,8 +778,10 @@ static void hrfd(orc *o)
     const int64_t N = o->ncell;
     const double yB = 0.5;
     double *ubx = (double *)malloc((o->nwall + 1) * sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int64_t w = 0; w < o->nwall; ++w)
         ubx[w] = o->utau[w] * orc_uplus(p->law, yB * o->utau[w] / p->nu, p->kappa, p->B) * o->tdir[3 * w];
+#pragma omp parallel for schedule(static)
     for (int64_t w = 0; w < o->nwall; ++w) {
         int64_t cell = o->wB[w];
         const double *t = &o->tdir[3 * w];
@@ -792,6 +823,7 @@ static void collide_and_sa(orc *o)
     const orc_params *p = &o->p;
     const int Q = p->q, D = o->D, nx = p->nx, ny = p->ny, nz = p->nz;
     const int64_t N = o->ncell;
+#pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -814,6 +846,7 @@ static void collide_and_sa(orc *o)
         return;
     }
     /* SA update from nu_tilde^n and the previous step's velocity */
+#pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {

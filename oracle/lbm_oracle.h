@@ -70,6 +70,10 @@ typedef struct orc_params {
 
 typedef struct orc orc;
 
+/* --- threads (OpenMP over lattice rows; results do not depend on them) --- */
+void orc_set_threads(int n); /* n > 0: use n threads */
+int orc_get_threads(void);
+
 /* --- whole-lattice oracle ------------------------------------------------ */
 orc *orc_create(const orc_params *p, const double *u0 /* D*ncell SoA, or NULL = zero */);
 void orc_destroy(orc *o);

@@ -432,6 +432,125 @@ def test_sa_rhs_terms():
         assert abs((r - r0) - (-U * upstream_diff)) < 1e-15
 
 
+# SA constants printed after eq. 14 and the definition of c_w1 there
+_K, _CB1, _CB2, _SIG, _CW2, _CW3, _CV1 = 0.41, 0.1355, 0.622, 2.0 / 3.0, 0.3, 2.0, 7.1
+_CW1 = _CB1 / _K ** 2 + (1.0 + _CB2) / _SIG
+
+
+def test_sa_constants_are_the_papers():
+    """The oracle's default SA constants are the values printed after eq. 14
+    (c_w1 follows from them: 3.2390678...)."""
+    p = O.params(q=9)
+    assert (p.kappa, p.cb1, p.cb2, p.cw2, p.cw3, p.cv1, p.rlim) == (0.41, 0.1355, 0.622, 0.3,
+                                                                      2.0, 7.1, 10.0)
+    assert abs(p.sigma - 2.0 / 3.0) < 1e-16
+    assert abs(_CW1 - 3.2390678167757287) < 1e-15
+
+
+def _eq15(yp):
+    """du+/dy+ of the SA constant-stress layer as printed (eq. 15)."""
+    ky = _K * yp
+    return (_CV1 ** 3 + ky ** 3) / (_CV1 ** 3 + (1.0 + ky) * ky ** 3)
+
+
+def _const_stress_rhs(yplus, y, utau=1e-3):
+    """Discrete SA right-hand side at the node y (lattice units, wall distance
+    d = y) of the constant-stress layer: nu_tilde = kappa u_tau y and u(y) the
+    integral of eq. 15 (taken by quadrature, independently of eq. 16), with
+    nu set so that y+ = yplus at the node.  Scaled by c_b1 u_tau^2."""
+    from scipy.integrate import quad
+    nu = y * utau / yplus
+    s = utau / nu
+    du_p = utau * quad(_eq15, yplus, (y + 1) * s, epsabs=0, epsrel=1e-13, limit=200)[0]
+    du_m = utau * quad(_eq15, (y - 1) * s, yplus, epsabs=0, epsrel=1e-13, limit=200)[0]
+    nt = lambda yy: _K * utau * yy
+    p = O.params(q=9, nu=nu)
+    um = [0.0, 0, 0, -du_m, 0, 0, 0, 0, 0]
+    up = [0.0, 0, 0, du_p, 0, 0, 0, 0, 0]
+    r = O.sa_rhs(p, 2, nt(y), [nt(y), nt(y - 1)], [nt(y), nt(y + 1)], [0.0, 0, 0], um, up, y)
+    return r / (_CB1 * utau ** 2)
+
+
+@pytest.mark.parametrize("yplus", [1.0, 3.0, 10.0, 30.0, 100.0])
+def test_sa_rhs_vanishes_in_constant_stress_layer(yplus):
+    """Constant total stress at finite chi = kappa y+ (eq. 15 is that layer's
+    profile): with nu_tilde = kappa u_tau y, eq. 13 gives S_tilde = u_tau /
+    (kappa y) exactly, because f_v2 = 1 - chi du+/dy+; so r = 1, f_w = 1, and
+    production c_b1 u_tau^2, destruction c_w1 kappa^2 u_tau^2 and diffusion
+    (1 + c_b2) kappa^2 u_tau^2 / sigma cancel by the definition of c_w1.
+    The discrete right-hand side vanishes at second order under refinement
+    at every y+ (this pins f_v1 and f_v2 where chi is finite)."""
+    r = [_const_stress_rhs(yplus, y) for y in (20.0, 40.0, 80.0, 160.0)]
+    assert abs(r[-1]) < 5e-4, r
+    for a, b in zip(r, r[1:]):
+        assert 3.8 < a / b < 4.2, r
+
+
+@pytest.mark.parametrize("chi", [2.0, 3.0])
+def test_sa_rhs_at_rest_with_negative_s_tilde(chi):
+    """At rest (S = 0) with a uniform nu_tilde at chi = 2 or 3, f_v2 < 0 and
+    S_tilde <= 0: the reading for that case switches production off and sets
+    r = r_lim = 10, where g = r + c_w2 (r^6 - r) ~ 3e5 and f_w (eq. 14) is its
+    large-g limit (1 + c_w3^6)^(1/6).  Only destruction remains:
+    -c_w1 (1 + c_w3^6)^(1/6) (nu_tilde / d)^2."""
+    nu = 1e-3
+    nt = chi * nu
+    p = O.params(q=9, nu=nu)
+    z3, z9 = [0.0] * 3, [0.0] * 9
+    for d in (0.5, 2.5, 7.0, 30.0, 1e3):
+        r = O.sa_rhs(p, 2, nt, [nt] * 3, [nt] * 3, z3, z9, z9, d)
+        ex = -_CW1 * (1.0 + _CW3 ** 6) ** (1.0 / 6.0) * (nt / d) ** 2
+        assert abs(r / ex - 1.0) < 1e-13, (d, r, ex)
+
+
+def _loglayer_rhs_a(a, y, utau=0.05, nu=1e-9):
+    """Log layer (chi -> infinity, so S_tilde = S) with nu_tilde = a kappa
+    u_tau y: r = a exactly, scaled right-hand side."""
+    p = O.params(q=9, nu=nu)
+    u = lambda yy: utau / _K * math.log(yy)
+    nt = lambda yy: a * _K * utau * yy
+    um = [u(y), 0, 0, u(y - 1), 0, 0, 0, 0, 0]
+    up = [u(y), 0, 0, u(y + 1), 0, 0, 0, 0, 0]
+    return O.sa_rhs(p, 2, nt(y), [nt(y), nt(y - 1)], [nt(y), nt(y + 1)], [u(y), 0, 0], um, up,
+                    y) / utau ** 2
+
+
+def test_sa_destruction_slope_at_r_equal_one():
+    """In the log layer with nu_tilde = a kappa u_tau y the right-hand side per
+    u_tau^2 is a c_b1 + a^2 (c_w1 kappa^2 - c_b1) - a^2 c_w1 kappa^2 f_w(a), so
+    its slope at a = 1 is -(c_b1 + c_w1 kappa^2 f_w'(1)); differentiating eq. 14
+    gives f_w'(1) = (1 + 5 c_w2) c_w3^6 / (1 + c_w3^6) (this pins the shape of
+    g and f_w between r = 1 and r_lim).  The discrete slope converges to it at
+    second order."""
+    ex = -(_CB1 + _CW1 * _K ** 2 * (1.0 + 5.0 * _CW2) * _CW3 ** 6 / (1.0 + _CW3 ** 6))
+    h = 1e-4
+    err = []
+    for y in (100.0, 200.0, 400.0):
+        sl = (_loglayer_rhs_a(1 + h, y) - _loglayer_rhs_a(1 - h, y)) / (2 * h)
+        err.append(abs(sl / ex - 1.0))
+    assert err[-1] < 3e-5, err
+    assert 3.5 < err[0] / err[1] < 4.5 and 3.5 < err[1] / err[2] < 4.5, err
+
+
+def test_sa_diffusion_second_order():
+    """Diffusion and the c_b2 term of eq. 11 for nu_tilde = A y^2 at rest, far
+    from walls (d large, so production and destruction are negligible): the
+    exact value is (1/sigma)[(nu + nu_tilde) nu_tilde'' + (1 + c_b2) nu_tilde'^2]
+    = (1/sigma)[2 A nu + (6 + 4 c_b2) A^2 y^2]; the discrete value approaches it
+    at second order in 1/y."""
+    nu, A = 1e-3, 1e-4
+    p = O.params(q=9, nu=nu)
+    z3, z9 = [0.0] * 3, [0.0] * 9
+    err = []
+    for y in (10.0, 20.0, 40.0):
+        nt = lambda yy: A * yy * yy
+        r = O.sa_rhs(p, 2, nt(y), [nt(y), nt(y - 1)], [nt(y), nt(y + 1)], z3, z9, z9, 1e12)
+        ex = (2 * A * nu + (6 + 4 * _CB2) * A * A * y * y) / _SIG
+        err.append(abs(r / ex - 1.0))
+    assert err[-1] < 2e-4, err
+    assert 3.5 < err[0] / err[1] < 4.5 and 3.5 < err[1] / err[2] < 4.5, err
+
+
 # ------------------------------------------------------------------ P14/15 ---
 def test_table2_dean():
     rows = np.loadtxt(os.path.join(GOLDEN, "table2_dean.txt"))
@@ -724,9 +843,10 @@ def test_yu_keeps_the_f_node_at_half():
 @pytest.mark.parametrize("q", [0.5, 0.3, 0.8])
 def test_sa_wall_distance_follows_the_wall_position(q):
     """With the walls q from the first and last nodes, node y sits y + q from
-    the bottom wall: from rest and a uniform nu_tilde the first step changes
-    nu_tilde by the SA right-hand side (pinned separately) at that distance,
-    here only destruction (no shear, no gradients)."""
+    the bottom wall.  From rest with a uniform nu_tilde at chi = 3 (f_v2 < 0,
+    so S_tilde <= 0: no production, r = r_lim) the first lattice step changes
+    nu_tilde at the interior nodes by destruction alone,
+    -c_w1 (1 + c_w3^6)^(1/6) (nu_tilde / d)^2 with d that distance."""
     ny, nu, nt0 = 12, 1e-3, 3e-3
     p = O.params(q=9, nx=3, ny=ny, nz=1, nu=nu, sa_on=1, scheme=O.BB_FIXED,
                  bb_interp=O.IBB_BOUZIDI if q != 0.5 else O.IBB_HALFWAY, wall_dist=q,
@@ -734,10 +854,9 @@ def test_sa_wall_distance_follows_the_wall_position(q):
     o = O.Oracle(p, np.zeros((2, 1, ny, 3)))
     o.step(1)
     nt = o.nt()[0, :, 1]
-    z3 = np.zeros(3)
     for y in range(2, ny - 2):  # neighbours away from the Dirichlet wall nodes
         d = min(y + q, ny - 1 - y + q)
-        ex = nt0 + O.sa_rhs(p, 2, nt0, [nt0] * 3, [nt0] * 3, z3, z3, z3, d)
+        ex = nt0 - _CW1 * (1.0 + _CW3 ** 6) ** (1.0 / 6.0) * (nt0 / d) ** 2
         assert abs(nt[y] - ex) < 1e-15 * nt0, (y, nt[y], ex)
 
 
