@@ -119,6 +119,10 @@ typedef enum { LBM_IBB_HALFWAY = 0, LBM_IBB_BOUZIDI = 1, LBM_IBB_YU = 2 } lbm_ib
  *   omega,1,1,1]; D3Q19 applies the same rule to its 19 central moments. */
 typedef enum { LBM_COLL_BGK = 0, LBM_COLL_CM = 1 } lbm_collision_t;
 
+/* Output type and location of the field exports (lbm_moments). */
+typedef enum { LBM_OUT_F64 = 0, LBM_OUT_F32 = 1 } lbm_out_dtype_t;
+typedef enum { LBM_ON_HOST = 0, LBM_ON_DEVICE = 1 } lbm_loc_t;
+
 /* Wall laws for the u_tau solve: Reichardt's law with log-law intercept B
  * (constant C = B - ln(kappa)/kappa), or the SA-consistent analytic law of
  * eq. 16 (derivative eq. 15). */
@@ -194,10 +198,18 @@ int64_t lbm_footprint(lbm_lattice_t lattice, int nx, int ny, int nz, const lbm_p
 
 /* Creates a lattice in the caller's device buffer dev_buf (>= footprint
  * bytes, 256-byte aligned) on device-stream `stream` (a hipStream_t; NULL is
- * the null stream) and initializes it: f = f_eq(rho0, u_init), nu_tilde =
- * nut_init_ratio * nu, then one wall-function pass.  Returns LBM_EINVAL for
- * nx < 1, ny < 4, nz != 1 with D2Q9, a plate with D3Q19 or nx < 4, HRFD with
- * D3Q19, nu <= 0, or a buffer that is too small. */
+ * the null stream) and initializes it.  The problem is the paper's: a
+ * uniform lattice (Sec. 2.1) for the periodic channel driven by a body force
+ * (Sec. 4.1.1) or the zero-pressure-gradient plate (Sec. 4.2.1) at a given
+ * viscosity (relaxation time from eq. 8 with nu + nu_t, eq. 10), wall scheme
+ * and wall law.  Initial state: populations at equilibrium
+ * f = f_eq(rho0, u_init), nu_tilde = nut_init_ratio * nu, then one
+ * wall-function pass (Sec. 3.1, eq. 20-22) that sets u_tau, the wall velocity
+ * and the Dirichlet nu_tilde of the wall cells.
+ * Ownership: dev_buf stays the caller's; *out is a host handle released by
+ * lbm_destroy.  Returns LBM_EINVAL for nx < 1, ny < 4, nz != 1 with D2Q9, a
+ * plate with D3Q19 or nx < 4, HRFD with D3Q19, nu <= 0, or a buffer that is
+ * too small; LBM_EHIP if a launch fails. */
 int lbm_create(lbm_lattice_t lattice, int nx, int ny, int nz, const lbm_params_t *p, void *dev_buf,
                int64_t buf_bytes, void *stream, lbm_t **out);
 
@@ -213,13 +225,20 @@ int lbm_set_wall_bc(lbm_t *h, lbm_wall_scheme_t scheme, double beta);
 /* Advances n >= 0 time steps, asynchronously on the handle's stream.  Each
  * step is one launch of the fused stream-collide-SA kernel and one of the
  * wall-function kernel; every reduce_every steps a reduction follows.
- * Returns LBM_EDIVERGED once a reduction has seen divergence. */
+ * Returns LBM_EDIVERGED once lbm_residual has seen divergence. */
 int lbm_step(lbm_t *h, int64_t n);
 
-/* Copies rho (ncell), u (D*ncell, SoA) and nu_t (ncell) of the last step into
- * caller buffers (NULL skips a field), as double, on the device (on_device =
- * 1, asynchronous) or the host (0, synchronous). */
-int lbm_moments(lbm_t *h, double *rho, double *u, double *nu_t, int on_device);
+/* Copies the macroscopic fields of the last step into caller buffers (NULL
+ * skips a field): the density rho = sum_i f_i (eq. 4, ncell values), the
+ * velocity u of eq. 5 with the half-force shift (D*ncell values, SoA:
+ * u[a*ncell + cell]) and the eddy viscosity nu_t = nu_tilde f_v1 (eq. 10,
+ * ncell values).  dtype: LBM_OUT_F64 (double) or LBM_OUT_F32 (float; exact
+ * for the FP32/FP16/BF16 storage variants, whose fields are float).
+ * where: LBM_ON_DEVICE (device buffers, asynchronous on the handle's stream,
+ * nothing allocated) or LBM_ON_HOST (host buffers, synchronous; the data is
+ * staged through a temporary device allocation freed before the call
+ * returns).  LBM_EINVAL for an unknown dtype or location. */
+int lbm_moments(lbm_t *h, void *rho, void *u, void *nu_t, int dtype, int where);
 
 /* Copies the SA working variable nu_tilde (ncell, double). */
 int lbm_nu_tilde(lbm_t *h, double *nt, int on_device);
@@ -229,9 +248,14 @@ int lbm_nu_tilde(lbm_t *h, double *nt, int on_device);
  * through an open boundary are reported as NaN.  Synchronous, host only. */
 int lbm_populations(lbm_t *h, double *f_host);
 
-/* Per wall cell: u_tau (>= 0), Cf = 2 (u_tau/u_ref)^2, the tangential
- * direction t (3 per cell) and the bounce-back wall velocity u_w (3 per cell).
- * Host buffers of n >= nwall entries (NULL skips); synchronous. */
+/* Per wall cell (in the wall-cell order above), from the wall function of
+ * the last step (Sec. 3.1, eq. 20-22): the friction velocity u_tau >= 0, the
+ * skin-friction coefficient Cf = 2 (u_tau / u_ref)^2 (the bulk form of
+ * Sec. 4.1.2.6; u_ref = U_b for the channel, U_inf for the plate), the
+ * tangential direction t of the velocity at F (3 per cell) and the wall
+ * velocity u_w of the bounce-back link rule (eq. 35 for the slip scheme;
+ * 3 per cell).  Host buffers of n >= nwall entries (NULL skips a field);
+ * synchronous.  LBM_EINVAL if n < nwall. */
 int lbm_wall(lbm_t *h, double *u_tau, double *cf, double *t, double *u_w, int64_t n);
 
 /* Number of cells / wall cells / steps taken. */

@@ -735,8 +735,10 @@ template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) 
     });
 }
 
-template <int Q, typename S, typename T>
-__global__ void __launch_bounds__(BLK) k_export_moments(KP P, bool odd_state, int cur, double *rho, double *u, double *nut)
+// rho (eq. 4, summed in double), u (the stored eq. 5 velocity) and nu_t
+// (eq. 10) of the last step, converted to the output type O.
+template <int Q, typename S, typename T, typename O>
+__global__ void __launch_bounds__(BLK) k_export_moments(KP P, bool odd_state, int cur, O *rho, O *u, O *nut)
 {
     constexpr int D = Lat<Q>::D;
     const int64_t cell = (int64_t)blockIdx.x * BLK + threadIdx.x;
@@ -748,15 +750,15 @@ __global__ void __launch_bounds__(BLK) k_export_moments(KP P, bool odd_state, in
         const S *A = (const S *)P.pops;
         double s = 0.0;
         sfor<Q>([&](auto ic) { s += (double)canon_f<Q, decltype(ic)::value, S, T>(P, A, x, y, z, cell, odd_state); });
-        rho[cell] = P.rho0 + s;
+        rho[cell] = (O)(P.rho0 + s);
     }
     if (u) {
         const T *uc = (const T *)P.u[cur];
-        for (int a = 0; a < D; ++a) u[a * N + cell] = (double)uc[a * N + cell];
+        for (int a = 0; a < D; ++a) u[a * N + cell] = (O)uc[a * N + cell];
     }
     if (nut) {
         const T nt = ((const T *)P.nt[cur])[cell];
-        nut[cell] = P.sa_on ? (double)nut_of<T>(P, nt) : 0.0;
+        nut[cell] = P.sa_on ? (O)nut_of<T>(P, nt) : (O)0;
     }
 }
 
@@ -1319,10 +1321,15 @@ template <int Q, typename S, typename T> struct Impl {
         HIPCHK(hipGetLastError());
         return LBM_OK;
     }
-    static int moments(lbm *h, bool odd_state, int cur, double *rho, double *u, double *nut)
+    static int moments(lbm *h, bool odd_state, int cur, void *rho, void *u, void *nut, int dtype)
     {
         dim3 grid((unsigned)((h->kp.ncell + BLK - 1) / BLK));
-        hipLaunchKernelGGL((k_export_moments<Q, S, T>), grid, dim3(BLK), 0, h->stream, h->kp, odd_state, cur, rho, u, nut);
+        if (dtype == LBM_OUT_F32)
+            hipLaunchKernelGGL((k_export_moments<Q, S, T, float>), grid, dim3(BLK), 0, h->stream, h->kp, odd_state, cur,
+                               (float *)rho, (float *)u, (float *)nut);
+        else
+            hipLaunchKernelGGL((k_export_moments<Q, S, T, double>), grid, dim3(BLK), 0, h->stream, h->kp, odd_state, cur,
+                               (double *)rho, (double *)u, (double *)nut);
         HIPCHK(hipGetLastError());
         return LBM_OK;
     }
@@ -1520,6 +1527,38 @@ int flush_timing(lbm *h)
     return LBM_OK;
 }
 
+// Device bytes of the requested moment fields in the output type.
+int64_t moments_bytes(const lbm *h, const void *rho, const void *u, const void *nut, int dtype)
+{
+    const int64_t e = dtype == LBM_OUT_F32 ? 4 : 8;
+    return e * h->kp.ncell * ((rho ? 1 : 0) + (u ? h->D : 0) + (nut ? 1 : 0));
+}
+
+// Moments to host buffers through device staging at `stage` (at least
+// moments_bytes bytes): export kernel, copies, one synchronization.
+int moments_via(lbm *h, char *stage, void *rho, void *u, void *nut, int dtype)
+{
+    const int64_t N = h->kp.ncell, e = dtype == LBM_OUT_F32 ? 4 : 8;
+    const bool odd_state = (h->step & 1) != 0;
+    const int cur = (int)(h->step & 1);
+    char *p = stage;
+    char *drho = rho ? p : nullptr;
+    p += rho ? N * e : 0;
+    char *du = u ? p : nullptr;
+    p += u ? h->D * N * e : 0;
+    char *dn = nut ? p : nullptr;
+    int rc = LBM_DISPATCH(h, moments, h, odd_state, cur, drho, du, dn, dtype);
+    hipError_t er = hipSuccess;
+    if (!rc && rho) er = hipMemcpyAsync(rho, drho, N * e, hipMemcpyDeviceToHost, h->stream);
+    if (!rc && er == hipSuccess && u) er = hipMemcpyAsync(u, du, h->D * N * e, hipMemcpyDeviceToHost, h->stream);
+    if (!rc && er == hipSuccess && nut) er = hipMemcpyAsync(nut, dn, N * e, hipMemcpyDeviceToHost, h->stream);
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    if (rc) return rc;
+    if (er != hipSuccess || e2 != hipSuccess)
+        return fail(LBM_EHIP, "moment copy failed: %s", hipGetErrorString(er != hipSuccess ? er : e2));
+    return LBM_OK;
+}
+
 int do_reduce(lbm *h)
 {
     const bool odd_state = (h->step & 1) != 0;
@@ -1688,27 +1727,20 @@ int lbm_step(lbm_t *h, int64_t n)
     return LBM_OK;
 }
 
-int lbm_moments(lbm_t *h, double *rho, double *u, double *nu_t, int on_device)
+int lbm_moments(lbm_t *h, void *rho, void *u, void *nu_t, int dtype, int where)
 {
     if (!h) return fail(LBM_ESTATE, "NULL handle");
-    const int64_t N = h->kp.ncell;
+    if (dtype != LBM_OUT_F64 && dtype != LBM_OUT_F32) return fail(LBM_EINVAL, "unknown output dtype %d", dtype);
+    if (where != LBM_ON_HOST && where != LBM_ON_DEVICE) return fail(LBM_EINVAL, "unknown location %d", where);
     const bool odd_state = (h->step & 1) != 0;
     const int cur = (int)(h->step & 1);
-    if (on_device) return LBM_DISPATCH(h, moments, h, odd_state, cur, rho, u, nu_t);
-    const size_t nb = (size_t)(N * (1 + h->D + 1)) * sizeof(double);
-    double *tmp = nullptr;
-    HIPCHK(hipMalloc((void **)&tmp, nb));
-    double *drho = rho ? tmp : nullptr, *du = u ? tmp + N : nullptr, *dn = nu_t ? tmp + N * (1 + h->D) : nullptr;
-    int rc = LBM_DISPATCH(h, moments, h, odd_state, cur, drho, du, dn);
-    hipError_t e = hipSuccess;
-    if (!rc && rho) e = hipMemcpyAsync(rho, drho, N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    if (!rc && e == hipSuccess && u) e = hipMemcpyAsync(u, du, (size_t)h->D * N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    if (!rc && e == hipSuccess && nu_t) e = hipMemcpyAsync(nu_t, dn, N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    hipError_t e2 = hipStreamSynchronize(h->stream);
+    if (where == LBM_ON_DEVICE) return LBM_DISPATCH(h, moments, h, odd_state, cur, rho, u, nu_t, dtype);
+    const int64_t bytes = moments_bytes(h, rho, u, nu_t, dtype);
+    char *tmp = nullptr;
+    if (bytes > 0) HIPCHK(hipMalloc((void **)&tmp, bytes));
+    int rc = moments_via(h, tmp, rho, u, nu_t, dtype);
     (void)hipFree(tmp);
-    if (rc) return rc;
-    if (e != hipSuccess || e2 != hipSuccess) return fail(LBM_EHIP, "moment copy failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
-    return LBM_OK;
+    return rc;
 }
 
 int lbm_nu_tilde(lbm_t *h, double *nt, int on_device)

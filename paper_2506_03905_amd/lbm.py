@@ -22,6 +22,9 @@ LBM_WALL_FIXED_BB, LBM_WALL_SLIP_BB, LBM_WALL_HRFD, LBM_WALL_CAI_DEGRIGNY = 0, 1
 LBM_IBB_HALFWAY, LBM_IBB_BOUZIDI, LBM_IBB_YU = 0, 1, 2
 LBM_LAW_REICHARDT, LBM_LAW_SA = 0, 1
 LBM_COLL_BGK, LBM_COLL_CM = 0, 1
+LBM_OUT_F64, LBM_OUT_F32 = 0, 1
+LBM_ON_HOST, LBM_ON_DEVICE = 0, 1
+OUT_DTYPE = {"f64": (LBM_OUT_F64, np.float64), "f32": (LBM_OUT_F32, np.float32)}
 
 PRECISION = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
 SCHEME = {"fixed_bb": LBM_WALL_FIXED_BB, "slip_bb": LBM_WALL_SLIP_BB, "hrfd": LBM_WALL_HRFD,
@@ -100,7 +103,7 @@ def lib() -> ctypes.CDLL:
         "lbm_set_velocity": (ctypes.c_int, [vp, vp, ctypes.c_int]),
         "lbm_set_wall_bc": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_double]),
         "lbm_step": (ctypes.c_int, [vp, i64]),
-        "lbm_moments": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int]),
+        "lbm_moments": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int]),
         "lbm_nu_tilde": (ctypes.c_int, [vp, vp, ctypes.c_int]),
         "lbm_populations": (ctypes.c_int, [vp, vp]),
         "lbm_wall": (ctypes.c_int, [vp, vp, vp, vp, vp, i64]),
@@ -217,13 +220,22 @@ class Lattice:
     def lbm_step(self, n: int = 1):
         _check(lib().lbm_step(self.h, n))
 
-    def lbm_moments(self):
-        rho = np.zeros(self.ncell)
-        u = np.zeros(self.D * self.ncell)
-        nut = np.zeros(self.ncell)
-        _check(lib().lbm_moments(self.h, _ptr(rho), _ptr(u), _ptr(nut), 0))
+    def lbm_moments(self, dtype: str = "f64"):
+        """(rho, u, nu_t) of the last step as host arrays of the given dtype."""
+        code, npt = OUT_DTYPE[dtype]
+        rho = np.zeros(self.ncell, npt)
+        u = np.zeros(self.D * self.ncell, npt)
+        nut = np.zeros(self.ncell, npt)
+        _check(lib().lbm_moments(self.h, _ptr(rho), _ptr(u), _ptr(nut), code, LBM_ON_HOST))
         return (rho.reshape(self.shape), u.reshape((self.D,) + self.shape),
                 nut.reshape(self.shape))
+
+    def lbm_moments_device(self, rho=None, u=None, nut=None, dtype: str = "f64"):
+        """The same into caller device tensors (None skips a field); asynchronous
+        on the lattice's stream."""
+        code, _ = OUT_DTYPE[dtype]
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        _check(lib().lbm_moments(self.h, ptr(rho), ptr(u), ptr(nut), code, LBM_ON_DEVICE))
 
     def lbm_nu_tilde(self):
         nt = np.zeros(self.ncell)
