@@ -240,6 +240,20 @@ int lbm_step(lbm_t *h, int64_t n);
  * returns).  LBM_EINVAL for an unknown dtype or location. */
 int lbm_moments(lbm_t *h, void *rho, void *u, void *nu_t, int dtype, int where);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lbm_moments
+ * with the same arguments and results, whose host path stages through a
+ * library-owned static device array of LBM_NOALLOC_SCRATCH_BYTES (one per
+ * GPU, held until the process ends) instead of a temporary allocation; it
+ * calls no allocating routine.  Returns LBM_EINVAL, with a message, when the
+ * requested fields need more staging than that (bytes = ncell * (4 or 8) *
+ * (number of requested scalar fields, u counting D)).  All calls on one GPU
+ * share that array: calls that overlap on one GPU (several threads, or calls
+ * racing on different streams) race and must be serialized by the caller.
+ * The device path (LBM_ON_DEVICE) uses no staging. */
+#define LBM_NOALLOC_SCRATCH_BYTES (32LL << 20)
+int lbm_moments_noalloc(lbm_t *h, void *rho, void *u, void *nu_t, int dtype, int where);
+
 /* Copies the SA working variable nu_tilde (ncell, double). */
 int lbm_nu_tilde(lbm_t *h, double *nt, int on_device);
 

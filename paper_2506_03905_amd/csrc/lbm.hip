@@ -34,6 +34,7 @@
 #include <string.h>
 
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -41,6 +42,12 @@
 #include "lbm_device.hpp"
 
 using namespace lbmd;
+
+// Staging memory of lbm_moments_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never uses this name as an
+// address: the device address of each GPU's copy comes from
+// hipGetSymbolAddress (scratch_on below) and is what kernels and copies get.
+static __device__ __align__(256) unsigned char scratch[LBM_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -1232,6 +1239,7 @@ struct lbm {
     char *base;
     int64_t bytes;
     hipStream_t stream;
+    int device;                 // the GPU holding the caller's buffer
     int64_t step;
     int64_t last_reduce_step;   // step of the last reduction (-1: none)
     int64_t prev_reduce_step;
@@ -1559,6 +1567,53 @@ int moments_via(lbm *h, char *stage, void *rho, void *u, void *nut, int dtype)
     return LBM_OK;
 }
 
+// The GPU that holds a device pointer (the current device if the runtime
+// cannot tell).
+int buffer_device(const void *p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) == hipSuccess && a.device >= 0) return a.device;
+    (void)hipGetLastError();
+    int d = 0;
+    (void)hipGetDevice(&d);
+    return d;
+}
+
+// Makes `dev` the current device for the lifetime of the guard.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Device address of `scratch` on GPU `dev`, looked up once per device with
+// that device current and kept.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[MAX_DEVICES] = {};
+
+int scratch_on(int dev, char **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(LBM_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        DeviceGuard g(dev);
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return fail(LBM_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch[dev] = (char *)ptr;
+    }
+    *out = g_scratch[dev];
+    return LBM_OK;
+}
+
 int do_reduce(lbm *h)
 {
     const bool odd_state = (h->step & 1) != 0;
@@ -1639,6 +1694,7 @@ int lbm_create(lbm_lattice_t lattice, int nx, int ny, int nz, const lbm_params_t
     h->base = (char *)dev_buf;
     h->bytes = buf_bytes;
     h->stream = (hipStream_t)stream;
+    h->device = buffer_device(dev_buf);
     h->timing = false;
     h->n_ev = 0;
     h->acc_step_ms = h->acc_wall_ms = 0.0;
@@ -1902,6 +1958,24 @@ int lbm_destroy(lbm_t *h)
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     delete h;
     return LBM_OK;
+}
+
+int lbm_moments_noalloc(lbm_t *h, void *rho, void *u, void *nu_t, int dtype, int where)
+{
+    if (!h) return fail(LBM_ESTATE, "NULL handle");
+    if (dtype != LBM_OUT_F64 && dtype != LBM_OUT_F32) return fail(LBM_EINVAL, "unknown output dtype %d", dtype);
+    if (where != LBM_ON_HOST && where != LBM_ON_DEVICE) return fail(LBM_EINVAL, "unknown location %d", where);
+    DeviceGuard g(h->device);
+    if (where == LBM_ON_DEVICE) return lbm_moments(h, rho, u, nu_t, dtype, where);  // allocates nothing
+    const int64_t bytes = moments_bytes(h, rho, u, nu_t, dtype);
+    if (bytes > LBM_NOALLOC_SCRATCH_BYTES)
+        return fail(LBM_EINVAL, "lbm_moments_noalloc: the requested fields need %lld bytes of staging, more than the %lld of its scratch; use lbm_moments",
+                    (long long)bytes, (long long)LBM_NOALLOC_SCRATCH_BYTES);
+    if (bytes == 0) return LBM_OK;
+    char *ptr = nullptr;
+    int rc = scratch_on(h->device, &ptr);
+    if (rc) return rc;
+    return moments_via(h, ptr, rho, u, nu_t, dtype);
 }
 
 const char *lbm_last_error(void) { return g_err; }

@@ -104,6 +104,7 @@ def lib() -> ctypes.CDLL:
         "lbm_set_wall_bc": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_double]),
         "lbm_step": (ctypes.c_int, [vp, i64]),
         "lbm_moments": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int]),
+        "lbm_moments_noalloc": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int]),
         "lbm_nu_tilde": (ctypes.c_int, [vp, vp, ctypes.c_int]),
         "lbm_populations": (ctypes.c_int, [vp, vp]),
         "lbm_wall": (ctypes.c_int, [vp, vp, vp, vp, vp, i64]),
@@ -229,6 +230,20 @@ class Lattice:
         _check(lib().lbm_moments(self.h, _ptr(rho), _ptr(u), _ptr(nut), code, LBM_ON_HOST))
         return (rho.reshape(self.shape), u.reshape((self.D,) + self.shape),
                 nut.reshape(self.shape))
+
+    def lbm_moments_noalloc(self, dtype: str = "f64", fields=("rho", "u", "nut")):
+        """lbm_moments to host arrays staged through the library's static
+        scratch (no device allocation); skipped fields come back as None."""
+        code, npt = OUT_DTYPE[dtype]
+        out = {"rho": np.zeros(self.ncell, npt) if "rho" in fields else None,
+               "u": np.zeros(self.D * self.ncell, npt) if "u" in fields else None,
+               "nut": np.zeros(self.ncell, npt) if "nut" in fields else None}
+        ptr = lambda a: _ptr(a) if a is not None else None
+        _check(lib().lbm_moments_noalloc(self.h, ptr(out["rho"]), ptr(out["u"]), ptr(out["nut"]), code,
+                                         LBM_ON_HOST))
+        return (None if out["rho"] is None else out["rho"].reshape(self.shape),
+                None if out["u"] is None else out["u"].reshape((self.D,) + self.shape),
+                None if out["nut"] is None else out["nut"].reshape(self.shape))
 
     def lbm_moments_device(self, rho=None, u=None, nut=None, dtype: str = "f64"):
         """The same into caller device tensors (None skips a field); asynchronous
