@@ -165,8 +165,8 @@ typedef struct lbm_params {
  * cells at the last step; l2_du_rel = ||u^n - u^(n-K)||_2 / (K ||u^n||_2) with K
  * the steps since the previous reduction; mean_u_tau over wall cells and its
  * relative change since the previous reduction (the convergence measure of
- * Sec. 4.1.1); nan_flag = 1 if any density or velocity was NaN/Inf or a
- * density <= 0. */
+ * Sec. 4.1.1; -1 when there is no previous reduction); nan_flag = 1 if any
+ * density or velocity was NaN/Inf or a density <= 0. */
 typedef struct lbm_residual {
     int64_t step;
     int64_t steps_since_previous;
@@ -222,10 +222,21 @@ int lbm_set_velocity(lbm_t *h, const double *u, int on_device);
 /* Selects the wall scheme (before the first step or between steps). */
 int lbm_set_wall_bc(lbm_t *h, lbm_wall_scheme_t scheme, double beta);
 
-/* Advances n >= 0 time steps, asynchronously on the handle's stream.  Each
- * step is one launch of the fused stream-collide-SA kernel and one of the
- * wall-function kernel; every reduce_every steps a reduction follows.
- * Returns LBM_EDIVERGED once lbm_residual has seen divergence. */
+/* Advances n >= 0 time steps, asynchronously on the handle's stream.  One
+ * step is the paper's time step: streaming (eq. 3) with the wall links
+ * (eq. 31 with the slip velocity of eq. 35, or the interpolated rules of
+ * eq. 36-37) or the regularized reconstruction at the wall cells (eq. 19,
+ * 23, 26-30), moments (eq. 4-5), collision with tau from nu + nu_t (eq. 7-8,
+ * 10; BGK or the central-moment operator), the Spalart-Allmaras update
+ * (eq. 11-14) and the wall function (Sec. 3.1, eq. 20-22).  Every
+ * reduce_every steps an FP64 reduction (mass, momentum, residual, mean u_tau,
+ * non-finite count) runs on the device, carried by the step itself on the
+ * channel's even steps; a sticky divergence flag is copied to pinned host
+ * memory without blocking and read by later lbm_step calls.  Returns
+ * LBM_EDIVERGED (and takes no further step) once a completed reduction has
+ * seen a NaN/Inf or a density <= 0; since the host runs ahead of the device,
+ * a divergence inside one call is normally reported by the next call (or at
+ * once by lbm_residual, which synchronizes).  LBM_EINVAL for n < 0. */
 int lbm_step(lbm_t *h, int64_t n);
 
 /* Copies the macroscopic fields of the last step into caller buffers (NULL
@@ -282,7 +293,9 @@ int64_t lbm_steps(const lbm_t *h);
  * nan_flag is set. */
 int lbm_residual(lbm_t *h, lbm_residual_t *out);
 
-/* Per-kernel timing with HIP events on the handle's stream. */
+/* Per-kernel timing with HIP events on the handle's stream: on = 0 off, 1 every
+ * launch, k > 1 only the launches of the two steps that start at a multiple
+ * of k (both step parities, fewer events between kernels). */
 int lbm_set_timing(lbm_t *h, int on);
 int lbm_get_timing(lbm_t *h, lbm_timing_t *out); /* synchronizes */
 
@@ -309,8 +322,11 @@ int lbm_destroy(lbm_t *h);
  *  - every other lattice on a second stream: each phase of a step (fused
  *    update, wall function, residual) is one launch over all resident
  *    lattices of a kind, whatever their number.
- * Every lattice stops on the device on convergence (residual of
- * lbm_residual_t below `tol` at a reduction step), divergence or `max_steps`.
+ * Every lattice stops on the device on convergence (at a reduction step:
+ * residual of lbm_residual_t below `tol`, or relative change of the mean
+ * u_tau since the previous reduction below `tol_utau`, the criterion of
+ * Sec. 4.1.1 taken over the reduction interval), divergence (a non-finite
+ * value or rho <= 0 seen by a reduction) or `max_steps`.
  * Results of one lattice do not depend on what else is resident.  The device
  * buffer also holds the slot descriptors, slot lists and block tables (about
  * 1/2000 of its size); the pool allocates a few pinned host pages.
@@ -326,6 +342,10 @@ typedef struct lbm_pool_status {
     double residual;    /* last residual ||u^n - u^(n-K)|| / (K ||u^n||) */
     double mean_u_tau;  /* mean u_tau over the wall cells at the last residual */
     int64_t footprint;  /* bytes of the pool buffer held by the slot */
+    double d_u_tau_rel; /* |mean u_tau - its previous value| / previous value over the
+                           last reduction interval; -1 before the second reduction */
+    int32_t converged_by; /* LBM_SLOT_CONVERGED: 1 residual < tol, 2 d_u_tau_rel < tol_utau */
+    int32_t pad_;
 } lbm_pool_status_t;
 
 /* dev_buf: caller-owned device memory (256-byte aligned) of `bytes`; the first
@@ -337,11 +357,12 @@ int lbm_pool_create(void *dev_buf, int64_t bytes, int max_slots, void *stream, l
 int64_t lbm_pool_free_bytes(const lbm_pool_t *pool);
 
 /* Admits one solve: the lattice is created in the pool buffer and initialized
- * (optionally from a host velocity field, as lbm_set_velocity).  Returns
+ * (optionally from a host velocity field, as lbm_set_velocity).  tol and
+ * tol_utau are the two convergence thresholds (0 switches one off).  Returns
  * LBM_ENOMEM (nothing changed) if no slot or no block of lbm_footprint()
  * bytes is free.  *slot receives the slot index. */
 int lbm_pool_admit(lbm_pool_t *pool, lbm_lattice_t lattice, int nx, int ny, int nz, const lbm_params_t *p,
-                   const double *u0_host, double tol, int64_t max_steps, int *slot);
+                   const double *u0_host, double tol, double tol_utau, int64_t max_steps, int *slot);
 
 /* Advances every running slot by up to `steps` steps and synchronizes. */
 int lbm_pool_step(lbm_pool_t *pool, int64_t steps);

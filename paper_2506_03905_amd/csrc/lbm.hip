@@ -33,6 +33,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <new>
@@ -60,6 +61,7 @@ constexpr int BLK = 256;  // threads per block of the per-cell kernels (128 and 
 #endif
 constexpr int NRED = 8;        // reduction slots
 constexpr int RED_BLOCKS = 2048;
+constexpr int RES_STICKY = 2 * NRED;  // result[RES_STICKY]: 1 once any reduction saw a bad cell
 
 // ---------------------------------------------------------------------------
 // Thread -> cell mapping.
@@ -325,12 +327,36 @@ __device__ __forceinline__ void sa_cell(const KP &P, const Cell &C, int rd, T nt
 }
 
 // ---------------------------------------------------------------------------
+// FP64 reductions.  Slots: 0 sum(rho - rho0), 1-3 sum(rho u), 4 sum |u -
+// u_snap|^2, 5 sum |u|^2, 6 count of cells with a non-finite value or rho <= 0,
+// 7 sum of u_tau over the wall cells.  Sums run in a fixed tree order.
+// ---------------------------------------------------------------------------
+template <int NT> __device__ __forceinline__ void block_sum(double (*sh)[NT], double *v, int nv)
+{
+    const int t = threadIdx.x;
+    for (int k = 0; k < nv; ++k) sh[k][t] = v[k];
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (int k = 0; k < nv; ++k) sh[k][t] += sh[k][t + s];
+        __syncthreads();
+    }
+}
+
+// One cell's share of slots 0-6, taken inside the step from the density and
+// velocity it has just computed (the snapshot u_snap is refreshed on the way).
+struct RedAcc {
+    double v[7];
+};
+
+// ---------------------------------------------------------------------------
 // finish: HRFD reconstruction (wall cells), moments, collision, AA store,
 // velocity, wall density and the Spalart-Allmaras update of one cell.
 // rd: ping-pong index of u^{n-1} / nu_tilde^n; results go to rd ^ 1.
 // ---------------------------------------------------------------------------
-template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false, bool IBB = false>
-__device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S *lds = nullptr)
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false, bool IBB = false,
+          bool RED = false>
+__device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S *lds = nullptr, RedAcc *ra = nullptr)
 {
     constexpr int D = Lat<Q>::D;
     using SS = Stor<S>;
@@ -494,6 +520,26 @@ __device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S 
     u_wr[N + cell] = uy;
     if (D == 3) u_wr[2 * N + cell] = uz;
     if (wi >= 0) P.wrho[wi] = (double)rho;
+    if constexpr (RED) {
+        T *__restrict__ us = (T *)P.usnap;
+        const T uv[3] = {ux, uy, uz};
+        const double rhod = (double)rho;
+        double du2 = 0.0, uu = 0.0;
+        bool bad = !(rhod > 0.0) || !isfinite(rhod);
+        ra->v[0] = (double)drho;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double ua = (double)uv[a], d = ua - (double)us[a * N + cell];
+            us[a * N + cell] = uv[a];
+            ra->v[1 + a] = rhod * ua;
+            uu += ua * ua;
+            du2 += d * d;
+            bad = bad || !isfinite(ua);
+        }
+        ra->v[4] = du2;
+        ra->v[5] = uu;
+        ra->v[6] = bad ? 1.0 : 0.0;
+    }
 
     // ---- Spalart-Allmaras update from nu_tilde^n and u^{n-1} -------------------
     // (the staged odd step runs it after its staged stores: cell_update)
@@ -508,8 +554,9 @@ __device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S 
 // ---------------------------------------------------------------------------
 // IBB: interpolated bounce-back links may be present (else the halfway rule
 // is compiled in alone, keeping the common kernels lean).
-template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false, bool IBB = false>
-__device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, int z, bool active)
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false, bool IBB = false,
+          bool RED = false>
+__device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, int z, bool active, RedAcc *ra = nullptr)
 {
     const int nx = P.nx;
     const int tid = threadIdx.x;
@@ -563,7 +610,7 @@ __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, i
         if (active && x == 0) zou_he(P, f);
     }
     if (!active) return;
-    finish<Q, S, T, ODD, PLATE, HRFD, CMC, false, IBB>(P, C, rd, f);
+    finish<Q, S, T, ODD, PLATE, HRFD, CMC, false, IBB, RED>(P, C, rd, f, nullptr, ra);
 }
 
 // plate mapping: rows aligned to the right end, nseg blocks per row
@@ -576,11 +623,14 @@ __device__ __forceinline__ void plate_block(int nx, int64_t b, int tid, int &x, 
 }
 
 // ---------------------------------------------------------------------------
-// k_step: one fused LBM-RANS step, one thread per cell.
+// k_step: one fused LBM-RANS step, one thread per cell.  RED (even channel
+// steps that end a reduction interval): each block also writes its FP64
+// partial sums of slots 0-6 to P.partials[blockIdx.x].
 // ---------------------------------------------------------------------------
-template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool IBB>
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool IBB, bool RED = false>
 __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
 {
+    static_assert(!RED || (!ODD && !PLATE), "the fused reduction is built for even channel steps");
     const int nx = P.nx, ny = P.ny;
     const int64_t N = P.ncell;
     const int tid = threadIdx.x;
@@ -614,7 +664,16 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         z = 0;
         active = x >= 0;
     }
-    cell_update<Q, S, T, ODD, PLATE, HRFD, CMC, false, IBB>(P, rd, x, y, z, active);
+    if constexpr (RED) {
+        RedAcc ra = {};
+        cell_update<Q, S, T, ODD, PLATE, HRFD, CMC, false, IBB, true>(P, rd, x, y, z, active, &ra);
+        __shared__ double sh[7][BLK];
+        block_sum<BLK>(sh, ra.v, 7);
+        if (tid == 0)
+            for (int k = 0; k < 7; ++k) P.partials[(int64_t)blockIdx.x * NRED + k] = sh[k][0];
+    } else {
+        cell_update<Q, S, T, ODD, PLATE, HRFD, CMC, false, IBB>(P, rd, x, y, z, active);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -811,6 +870,7 @@ __global__ void __launch_bounds__(BLK) k_init(KP P, const double *u0, double ux0
     }
     ((T *)P.nt[0])[cell] = (T)ntinit;
     ((T *)P.nt[1])[cell] = (T)ntinit;
+    if (cell == 0) P.result[RES_STICKY] = 0.0;
 }
 
 __global__ void k_init_wall(KP P)
@@ -832,17 +892,6 @@ __global__ void k_init_wall(KP P)
 // slots: 0 sum(rho - rho0), 1-3 sum(rho u), 4 sum |u - usnap|^2, 5 sum |u|^2,
 // 6 bad-value count.
 // ---------------------------------------------------------------------------
-template <int NT> __device__ __forceinline__ void block_sum(double (*sh)[NT], double *v, int nv)
-{
-    const int t = threadIdx.x;
-    for (int k = 0; k < nv; ++k) sh[k][t] = v[k];
-    __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if (t < s)
-            for (int k = 0; k < nv; ++k) sh[k][t] += sh[k][t + s];
-        __syncthreads();
-    }
-}
 
 // Block b of nb: FP64 partial sums (slots 0-7) over its share of the cells,
 // written to P.partials[b]; the velocity snapshot is refreshed on the way.
@@ -890,15 +939,23 @@ template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) 
     reduce_part<Q, S, T>(P, odd_state, cur, blockIdx.x, gridDim.x);
 }
 
+// Second pass of a lattice's reduction: slots 0-6 from the nblocks partials
+// (written by k_reduce or by a fused k_step), slot 7 from the wall cells'
+// u_tau; result slot `slot` gets the sums, and the sticky divergence flag
+// P.result[RES_STICKY] is raised when this reduction saw a bad cell.
 __global__ void __launch_bounds__(BLK) k_reduce_final(KP P, int nblocks, int slot)
 {
     __shared__ double sh[8][BLK];
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nblocks; b += BLK)
-        for (int k = 0; k < 8; ++k) acc[k] += P.partials[b * NRED + k];
+    for (int64_t b = threadIdx.x; b < nblocks; b += BLK)
+        for (int k = 0; k < 7; ++k) acc[k] += P.partials[b * NRED + k];
+    for (int64_t w = threadIdx.x; w < P.nwall; w += BLK) acc[7] += P.utau[w];
     block_sum<BLK>(sh, acc, 8);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         for (int k = 0; k < 8; ++k) P.result[slot * NRED + k] = sh[k][0];
+        const bool bad = sh[6][0] > 0.0 || !isfinite(sh[4][0]) || !isfinite(sh[5][0]);
+        if (bad) P.result[RES_STICKY] = 1.0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -923,25 +980,41 @@ struct SlotDesc {
     int64_t snap_step;  // step of the previous residual snapshot
     int64_t stop_step;  // step at which the lattice stopped
     double tol, residual, mean_utau;
-    int status, reduce_every, variant, pad_;
+    double tol_utau;         // Delta u_tau / u_tau criterion (0: off)
+    double prev_mean_utau;   // mean u_tau at the previous reduction (0: none yet)
+    double d_utau_rel;       // its relative change over the last interval (-1: none yet)
+    int status, reduce_every, variant, conv_by;  // conv_by: 1 residual, 2 u_tau
 };
 
 // residual r = ||u - u_snap|| / (K ||u||), mean u_tau and the stop decision
 // from the FP64 sums {du^2, u^2, non-finite count, sum u_tau}; thread 0 only.
+// A lattice converges at a reduction step when r < tol, or when the mean
+// friction velocity changed by less than tol_utau (relative) since the
+// previous reduction (the criterion of Sec. 4.1.1, over the reduction
+// interval); conv_by records which.
 __device__ __forceinline__ void slot_verdict(SlotDesc &SD, int64_t nwall, int64_t step, double du2, double uu,
                                              double bad, double sutau, bool red_now)
 {
     const double K = (double)(step - SD.snap_step);
     const double r = uu > 0.0 ? sqrt(du2) / (K * sqrt(uu)) : 0.0;
+    const double mu = nwall > 0 ? sutau / (double)nwall : 0.0;
+    const double prev = SD.prev_mean_utau;
+    SD.d_utau_rel = prev > 0.0 ? fabs(mu - prev) / prev : -1.0;
+    SD.prev_mean_utau = mu;
     SD.residual = r;
-    SD.mean_utau = nwall > 0 ? sutau / (double)nwall : 0.0;
+    SD.mean_utau = mu;
     SD.snap_step = step;
-    if (bad > 0.0 || !isfinite(r))
+    if (bad > 0.0 || !isfinite(r) || !isfinite(mu)) {
         SD.status = SLOT_DIVERGED;
-    else if (red_now && r < SD.tol)
+    } else if (red_now && r < SD.tol) {
         SD.status = SLOT_CONVERGED;
-    else if (step >= SD.max_steps)
+        SD.conv_by = 1;
+    } else if (red_now && SD.tol_utau > 0.0 && SD.d_utau_rel >= 0.0 && SD.d_utau_rel < SD.tol_utau) {
+        SD.status = SLOT_CONVERGED;
+        SD.conv_by = 2;
+    } else if (step >= SD.max_steps) {
         SD.status = SLOT_CAPPED;
+    }
     if (SD.status != SLOT_RUNNING) SD.stop_step = step;
 }
 
@@ -1222,7 +1295,10 @@ bool make_layout(int Q, int nx, int ny, int nz, const lbm_params_t *p, Layout *L
     L->wrho = o; o = align256(o + (nw + 1) * 8);
     L->ubwf = o; o = align256(o + (nw + 1) * 8);
     L->gan = o; o = align256(o + (nw + 1) * 8);
-    L->partials = o; o = align256(o + (int64_t)RED_BLOCKS * NRED * 8);
+    // one partial-sum row per block of the standalone reduction or of the step
+    // (fused reduction): the larger of the row-mapped and flat grids
+    const int64_t step_blocks = std::max((int64_t)ny * nz * ((nx + BLK - 1) / BLK), (N + BLK - 1) / BLK);
+    L->partials = o; o = align256(o + std::max((int64_t)RED_BLOCKS, step_blocks) * NRED * 8);
     L->result = o; o = align256(o + 32 * 8);
     L->ibuf = o; o = align256(o + (p->bb_interp != LBM_IBB_HALFWAY ? (int64_t)Q * nw * 8 : 0));
     L->total = o;
@@ -1246,6 +1322,13 @@ struct lbm {
     int reduce_count;
     bool diverged;
     bool timing;
+    int timing_every;         // time 2 consecutive steps in every timing_every (1: all)
+    bool chain_open;          // the last launch on the stream was followed by an event
+    // non-blocking divergence check: the sticky flag of the reductions is
+    // copied to pinned host memory after each periodic reduction
+    double *flag_host;
+    hipEvent_t flag_ev;
+    bool flag_pending;
     // One chain of events on the stream; the interval that ends at event k
     // belongs to ev_kind[k] (a k_step or k_wall launch, or nothing timed).
     // One event per launch keeps the instrumentation light.
@@ -1260,16 +1343,22 @@ namespace {
 
 template <int Q, typename S, typename T> struct Impl {
     static constexpr int D = Lat<Q>::D;
-    template <bool PLATE, bool HRFD, bool IBB> static void (*pick(bool odd, bool cm))(KP, int)
+    // red: the even channel step that ends a reduction interval (fused reduction)
+    template <bool PLATE, bool HRFD, bool IBB> static void (*pick(bool odd, bool cm, bool red))(KP, int)
     {
+        if constexpr (!PLATE) {
+            if (red && !odd)
+                return cm ? k_step<Q, S, T, false, PLATE, HRFD, true, IBB, true> : k_step<Q, S, T, false, PLATE, HRFD, false, IBB, true>;
+        }
         if (cm) return odd ? k_step<Q, S, T, true, PLATE, HRFD, true, IBB> : k_step<Q, S, T, false, PLATE, HRFD, true, IBB>;
         return odd ? k_step<Q, S, T, true, PLATE, HRFD, false, IBB> : k_step<Q, S, T, false, PLATE, HRFD, false, IBB>;
     }
-    template <bool PLATE> static void (*pick_bb(bool odd, bool cm, bool ibb))(KP, int)
+    template <bool PLATE> static void (*pick_bb(bool odd, bool cm, bool ibb, bool red))(KP, int)
     {
-        return ibb ? pick<PLATE, false, true>(odd, cm) : pick<PLATE, false, false>(odd, cm);
+        return ibb ? pick<PLATE, false, true>(odd, cm, red) : pick<PLATE, false, false>(odd, cm, red);
     }
-    static int step(lbm *h, bool odd, int rd)
+    // launches one step; *nblocks (if given) receives the grid size
+    static int step(lbm *h, bool odd, int rd, bool red, int64_t *nblocks)
     {
         const KP &P = h->kp;
         const bool plate = h->p.flow == LBM_FLOW_PLATE;
@@ -1281,18 +1370,20 @@ template <int Q, typename S, typename T> struct Impl {
             grid = dim3((unsigned)((P.ncell + BLK - 1) / BLK));
         const bool cm = h->p.collision == LBM_COLL_CM;
         const bool ibb = h->p.bb_interp != LBM_IBB_HALFWAY;
+        red = red && !plate && !odd;
         void (*kern)(KP, int) = nullptr;
         if constexpr (Q == 9) {
             if (plate) {
-                if (hrfd) kern = pick<true, true, false>(odd, cm);
-                else kern = pick_bb<true>(odd, cm, ibb);
+                if (hrfd) kern = pick<true, true, false>(odd, cm, false);
+                else kern = pick_bb<true>(odd, cm, ibb, false);
             } else {
-                if (hrfd) kern = pick<false, true, false>(odd, cm);
-                else kern = pick_bb<false>(odd, cm, ibb);
+                if (hrfd) kern = pick<false, true, false>(odd, cm, red);
+                else kern = pick_bb<false>(odd, cm, ibb, red);
             }
         } else {
-            kern = pick_bb<false>(odd, cm, ibb);
+            kern = pick_bb<false>(odd, cm, ibb, red);
         }
+        if (nblocks) *nblocks = grid.x;
         hipLaunchKernelGGL(kern, grid, dim3(BLK), 0, h->stream, P, rd);
         HIPCHK(hipGetLastError());
         return LBM_OK;
@@ -1319,13 +1410,16 @@ template <int Q, typename S, typename T> struct Impl {
         }
         return wall(h, 0);
     }
-    static int reduce(lbm *h, bool odd_state, int cur, int slot)
+    // fused_nb > 0: the step just launched wrote fused_nb partial rows
+    static int reduce(lbm *h, bool odd_state, int cur, int slot, int64_t fused_nb)
     {
-        int nb = (int)((h->kp.ncell + BLK - 1) / BLK);
-        if (nb > RED_BLOCKS) nb = RED_BLOCKS;
-        hipLaunchKernelGGL((k_reduce<Q, S, T>), dim3(nb), dim3(BLK), 0, h->stream, h->kp, odd_state, cur);
-        HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLK), 0, h->stream, h->kp, nb, slot);
+        int64_t nb = fused_nb;
+        if (nb <= 0) {
+            nb = std::min((h->kp.ncell + BLK - 1) / BLK, (int64_t)RED_BLOCKS);
+            hipLaunchKernelGGL((k_reduce<Q, S, T>), dim3((unsigned)nb), dim3(BLK), 0, h->stream, h->kp, odd_state, cur);
+            HIPCHK(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLK), 0, h->stream, h->kp, (int)nb, slot);
         HIPCHK(hipGetLastError());
         return LBM_OK;
     }
@@ -1495,6 +1589,7 @@ int run_init(lbm *h, const double *u0dev)
     h->prev_reduce_step = 0;
     h->reduce_count = 0;
     h->diverged = false;
+    h->flag_pending = false;  // the device-side sticky flag is cleared by the init kernel
     return LBM_DISPATCH(h, init, h, u0dev);
 }
 
@@ -1614,12 +1709,39 @@ int scratch_on(int dev, char **out)
     return LBM_OK;
 }
 
-int do_reduce(lbm *h)
+// Reads the divergence flag copied after an earlier reduction if that copy
+// has completed (never waits).
+int poll_flag(lbm *h)
+{
+    if (!h->flag_pending) return LBM_OK;
+    const hipError_t e = hipEventQuery(h->flag_ev);
+    if (e == hipErrorNotReady) return LBM_OK;
+    if (e != hipSuccess) return fail(LBM_EHIP, "hipEventQuery: %s", hipGetErrorString(e));
+    h->flag_pending = false;
+    if (*h->flag_host != 0.0) h->diverged = true;
+    return LBM_OK;
+}
+
+// Queues the copy of the sticky divergence flag to pinned host memory.
+int push_flag(lbm *h)
+{
+    if (!h->flag_host) {
+        HIPCHK(hipHostMalloc((void **)&h->flag_host, sizeof(double), hipHostMallocDefault));
+        *h->flag_host = 0.0;
+        HIPCHK(hipEventCreateWithFlags(&h->flag_ev, hipEventDisableTiming));
+    }
+    HIPCHK(hipMemcpyAsync(h->flag_host, h->kp.result + RES_STICKY, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipEventRecord(h->flag_ev, h->stream));
+    h->flag_pending = true;
+    return LBM_OK;
+}
+
+int do_reduce(lbm *h, int64_t fused_nb = 0)
 {
     const bool odd_state = (h->step & 1) != 0;
     const int cur = (int)(h->step & 1);
     const int slot = h->reduce_count & 1;
-    int rc = LBM_DISPATCH(h, reduce, h, odd_state, cur, slot);
+    int rc = LBM_DISPATCH(h, reduce, h, odd_state, cur, slot, fused_nb);
     if (rc) return rc;
     h->prev_reduce_step = h->last_reduce_step < 0 ? 0 : h->last_reduce_step;
     h->last_reduce_step = h->step;
@@ -1696,6 +1818,11 @@ int lbm_create(lbm_lattice_t lattice, int nx, int ny, int nz, const lbm_params_t
     h->stream = (hipStream_t)stream;
     h->device = buffer_device(dev_buf);
     h->timing = false;
+    h->timing_every = 1;
+    h->chain_open = false;
+    h->flag_host = nullptr;
+    h->flag_ev = nullptr;
+    h->flag_pending = false;
     h->n_ev = 0;
     h->acc_step_ms = h->acc_wall_ms = 0.0;
     h->acc_step_n = h->acc_wall_n = 0;
@@ -1753,32 +1880,43 @@ int lbm_step(lbm_t *h, int64_t n)
 {
     if (!h) return fail(LBM_ESTATE, "NULL handle");
     if (n < 0) return fail(LBM_EINVAL, "negative step count");
+    int rc = poll_flag(h);
+    if (rc) return rc;
     if (h->diverged) return fail(LBM_EDIVERGED, "the solution diverged at or before step %lld", (long long)h->last_reduce_step);
-    int rc;
-    // the first interval of this call starts here (host time before the call
-    // is not counted)
-    if (n > 0 && h->timing && (rc = record(h, EV_NONE))) return rc;
+    // host time before the call is not counted: the first timed step opens a
+    // new chain of events
+    h->chain_open = false;
     for (int64_t s = 0; s < n; ++s) {
         const int64_t next = h->step + 1;
         const bool odd = (next & 1) != 0;
         const int rd = (int)(h->step & 1);
-        rc = LBM_DISPATCH(h, step, h, odd, rd);
+        const bool red = h->p.reduce_every > 0 && next % h->p.reduce_every == 0;
+        const bool timed = h->timing && (h->timing_every <= 1 || h->step % h->timing_every < 2);
+        if (timed && !h->chain_open && (rc = record(h, EV_NONE))) return rc;
+        int64_t nb = 0;
+        rc = LBM_DISPATCH(h, step, h, odd, rd, red, &nb);
         if (rc) return rc;
-        if (h->timing && (rc = record(h, EV_STEP))) return rc;
+        // the channel's even steps carry the reduction's first pass
+        const bool fused = red && !odd && h->p.flow == LBM_FLOW_CHANNEL;
+        if (timed && (rc = record(h, EV_STEP))) return rc;
         rc = LBM_DISPATCH(h, wall, h, rd ^ 1);
         if (rc) return rc;
-        if (h->timing && (rc = record(h, EV_WALL))) return rc;
+        if (timed && (rc = record(h, EV_WALL))) return rc;
+        h->chain_open = timed;
         h->step = next;
-        if (h->p.reduce_every > 0 && h->step % h->p.reduce_every == 0) {
-            rc = do_reduce(h);
+        if (red) {
+            rc = do_reduce(h, fused ? nb : 0);
             if (rc) return rc;
-            if (h->timing && (rc = record(h, EV_NONE))) return rc;
+            if ((rc = poll_flag(h))) return rc;  // an earlier reduction's flag, if already back
+            if ((rc = push_flag(h))) return rc;
+            if (h->chain_open && (rc = record(h, EV_NONE))) return rc;
         }
         if (h->timing && h->n_ev >= 8192) {
             rc = flush_timing(h);
             if (rc) return rc;
-            if (s + 1 < n && (rc = record(h, EV_NONE))) return rc;
+            h->chain_open = false;
         }
+        if (h->diverged) return fail(LBM_EDIVERGED, "the solution diverged before step %lld", (long long)h->step);
     }
     return LBM_OK;
 }
@@ -1882,7 +2020,7 @@ int lbm_residual(lbm_t *h, lbm_residual_t *out)
     const double nw = h->kp.nwall > 0 ? (double)h->kp.nwall : 1.0;
     out->mean_u_tau = c[7] / nw;
     const double prev = q[7] / nw;
-    out->d_u_tau_rel = (h->reduce_count >= 2 && prev > 0.0) ? fabs(out->mean_u_tau - prev) / prev : 0.0;
+    out->d_u_tau_rel = (h->reduce_count >= 2 && prev > 0.0) ? fabs(out->mean_u_tau - prev) / prev : -1.0;
     out->nan_flag = c[6] > 0.0 || !isfinite(c[4]) || !isfinite(c[5]) ? 1.0 : 0.0;
     if (out->nan_flag != 0.0) {
         h->diverged = true;
@@ -1894,9 +2032,11 @@ int lbm_residual(lbm_t *h, lbm_residual_t *out)
 int lbm_set_timing(lbm_t *h, int on)
 {
     if (!h) return fail(LBM_ESTATE, "NULL handle");
+    if (on < 0) return fail(LBM_EINVAL, "timing period must be >= 0");
     int rc = flush_timing(h);
     if (rc) return rc;
     h->timing = on != 0;
+    h->timing_every = on > 1 ? on : 1;
     h->acc_step_ms = h->acc_wall_ms = 0.0;
     h->acc_step_n = h->acc_wall_n = 0;
     return LBM_OK;
@@ -1948,6 +2088,7 @@ int lbm_load(lbm_t *h, const void *host, int64_t bytes)
     h->prev_reduce_step = h->step;
     h->reduce_count = 0;
     h->diverged = false;
+    h->flag_pending = false;  // a copy queued before the load is stale
     return LBM_OK;
 }
 
@@ -1956,6 +2097,8 @@ int lbm_destroy(lbm_t *h)
     if (!h) return fail(LBM_ESTATE, "NULL handle");
     (void)hipStreamSynchronize(h->stream);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    if (h->flag_ev) (void)hipEventDestroy(h->flag_ev);
+    if (h->flag_host) (void)hipHostFree(h->flag_host);
     delete h;
     return LBM_OK;
 }
@@ -2002,7 +2145,8 @@ struct PoolSlot {
     int64_t off = 0, bytes = 0;
     int status = SLOT_IDLE;
     int key = 0;  // launch kind: see slot_key
-    double residual = 0.0, mean_utau = 0.0;
+    double residual = 0.0, mean_utau = 0.0, d_utau_rel = -1.0;
+    int conv_by = 0;
     int64_t steps = 0, max_steps = 0, reduce_every = 100;
     int64_t step_blocks = 0, wall_blocks = 0;
 };
@@ -2188,6 +2332,8 @@ void harvest(lbm_pool *pl, int gi)
         S.status = d.status;
         S.residual = d.residual;
         S.mean_utau = d.mean_utau;
+        S.d_utau_rel = d.d_utau_rel;
+        S.conv_by = d.conv_by;
         S.steps = d.step;
         S.h->step = d.step;
         S.h->last_reduce_step = -1;
@@ -2383,14 +2529,15 @@ int64_t lbm_pool_free_bytes(const lbm_pool_t *pl)
 }
 
 int lbm_pool_admit(lbm_pool_t *pl, lbm_lattice_t lattice, int nx, int ny, int nz, const lbm_params_t *p,
-                   const double *u0_host, double tol, int64_t max_steps, int *slot)
+                   const double *u0_host, double tol, double tol_utau, int64_t max_steps, int *slot)
 {
     if (!pl) return fail(LBM_ESTATE, "NULL pool");
     if (!slot) return fail(LBM_EINVAL, "slot is NULL");
     *slot = -1;
     int64_t need = lbm_footprint(lattice, nx, ny, nz, p);
     if (need < 0) return (int)need;
-    if (!(tol >= 0.0) || max_steps < 1) return fail(LBM_EINVAL, "tol must be >= 0 and max_steps >= 1");
+    if (!(tol >= 0.0) || !(tol_utau >= 0.0) || max_steps < 1)
+        return fail(LBM_EINVAL, "tol and tol_utau must be >= 0 and max_steps >= 1");
     int idx = -1;
     for (int i = 0; i < pl->max_slots; ++i)
         if (!pl->slots[i].used) {
@@ -2446,6 +2593,10 @@ int lbm_pool_admit(lbm_pool_t *pl, lbm_lattice_t lattice, int nx, int ny, int nz
     d.stop_step = 0;
     d.max_steps = max_steps;
     d.tol = tol;
+    d.tol_utau = tol_utau;
+    d.prev_mean_utau = 0.0;
+    d.d_utau_rel = -1.0;
+    d.conv_by = 0;
     d.status = SLOT_RUNNING;
     d.reduce_every = (int)S.reduce_every;
     d.variant = S.key;
@@ -2507,6 +2658,8 @@ int lbm_pool_poll(lbm_pool_t *pl, int slot, lbm_pool_status_t *out)
     out->steps = S.steps;
     out->residual = S.residual;
     out->mean_u_tau = S.mean_utau;
+    out->d_u_tau_rel = S.d_utau_rel;
+    out->converged_by = S.conv_by;
     out->footprint = S.bytes;
     return LBM_OK;
 }

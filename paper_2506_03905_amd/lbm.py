@@ -67,7 +67,8 @@ class lbm_pool_status_t(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int32), ("batched", ctypes.c_int32), ("steps", ctypes.c_int64),
         ("residual", ctypes.c_double), ("mean_u_tau", ctypes.c_double),
-        ("footprint", ctypes.c_int64),
+        ("footprint", ctypes.c_int64), ("d_u_tau_rel", ctypes.c_double),
+        ("converged_by", ctypes.c_int32), ("pad_", ctypes.c_int32),
     ]
 
 
@@ -122,7 +123,7 @@ def lib() -> ctypes.CDLL:
         "lbm_pool_create": (ctypes.c_int, [vp, i64, ctypes.c_int, vp, ctypes.POINTER(vp)]),
         "lbm_pool_free_bytes": (i64, [vp]),
         "lbm_pool_admit": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                          P, vp, ctypes.c_double, i64,
+                                          P, vp, ctypes.c_double, ctypes.c_double, i64,
                                           ctypes.POINTER(ctypes.c_int)]),
         "lbm_pool_step": (ctypes.c_int, [vp, i64]),
         "lbm_pool_pump": (ctypes.c_int, [vp, i64, ctypes.POINTER(ctypes.c_int)]),
@@ -280,8 +281,10 @@ class Lattice:
             _check(rc)
         return out
 
-    def lbm_set_timing(self, on: bool):
-        _check(lib().lbm_set_timing(self.h, 1 if on else 0))
+    def lbm_set_timing(self, on: bool, every: int = 1):
+        """Per-launch kernel timing; every > 1 times 2 consecutive steps in
+        every `every` steps (both step parities, fewer events on the stream)."""
+        _check(lib().lbm_set_timing(self.h, (every if every > 1 else 1) if on else 0))
 
     def lbm_get_timing(self) -> dict:
         t = lbm_timing_t()
@@ -349,7 +352,8 @@ class Pool:
     def lbm_pool_free_bytes(self) -> int:
         return int(lib().lbm_pool_free_bytes(self.h))
 
-    def lbm_pool_admit(self, lattice, nx, ny, nz, p, u0=None, tol=1e-8, max_steps=10 ** 6):
+    def lbm_pool_admit(self, lattice, nx, ny, nz, p, u0=None, tol=1e-8, max_steps=10 ** 6,
+                       tol_utau=0.0):
         """Returns the slot index, or None when the pool cannot hold it (LBM_ENOMEM)."""
         slot = ctypes.c_int(-1)
         ptr = None
@@ -357,7 +361,7 @@ class Pool:
             u0 = np.ascontiguousarray(np.asarray(u0, dtype=np.float64))
             ptr = _ptr(u0)
         rc = lib().lbm_pool_admit(self.h, lattice, nx, ny, nz, ctypes.byref(p), ptr, tol,
-                                  int(max_steps), ctypes.byref(slot))
+                                  tol_utau, int(max_steps), ctypes.byref(slot))
         if rc == LBM_ENOMEM:
             return None
         _check(rc)
@@ -379,7 +383,8 @@ class Pool:
         _check(lib().lbm_pool_poll(self.h, slot, ctypes.byref(st)))
         return {"status": st.status, "batched": bool(st.batched), "steps": st.steps,
                 "residual": st.residual, "mean_u_tau": st.mean_u_tau,
-                "footprint": st.footprint}
+                "footprint": st.footprint, "d_u_tau_rel": st.d_u_tau_rel,
+                "converged_by": st.converged_by}
 
     def lbm_pool_lattice(self, slot: int) -> Lattice:
         h = lib().lbm_pool_lattice(self.h, slot)

@@ -6,9 +6,12 @@ are free; all resident lattices advance together in two groups that run
 concurrently (small lattices in persistent launches, the others in
 multi-lattice launches on a second stream), each group relaunched as soon as
 its previous chunk of steps ends (lbm_pool_pump); a lattice leaves the pool
-when its residual ||u^n - u^(n-K)|| / (K ||u^n||) falls below the tolerance,
-when it diverges or when it reaches the step cap.  The sequential baseline
-runs the same requests one at a time with the plain per-lattice path.
+when its residual ||u^n - u^(n-K)|| / (K ||u^n||) falls below `tol`, when the
+mean friction velocity changes by less than `tol_utau` (relative) between two
+reductions K steps apart (the paper's criterion, Sec. 4.1.1), when it
+diverges or when it reaches the step cap; the result says which.  The
+sequential baseline runs the same requests one at a time with the plain
+per-lattice path and the same criteria.
 
 Request -> lattice (Sec. 4.1.1 and 4.2.1 of the paper, sizes from the
 serving workload): channel 4 x Ny, Re_tau from Dean's correlation at Ma 0.05;
@@ -55,13 +58,20 @@ def footprint(req: dict) -> int:
 def _summary(results: dict, makespan: float) -> dict:
     lat = np.array([r["latency"] for r in results.values()])
     st = [r["status"] for r in results.values()]
+    by = [r.get("converged_by", 0) for r in results.values()]
+    conv = np.array([r["latency"] for r in results.values() if r["status"] == L.LBM_SLOT_CONVERGED])
     return {
         "solves": len(results),
         "solves_per_s": len(results) / makespan if makespan > 0 else 0.0,
         "makespan_s": makespan,
         "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
         "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
+        # time-to-converged over the requests that converged
+        "p50_converged_s": float(np.percentile(conv, 50)) if len(conv) else None,
+        "p99_converged_s": float(np.percentile(conv, 99)) if len(conv) else None,
         "converged": sum(s == L.LBM_SLOT_CONVERGED for s in st),
+        "converged_by_residual": sum(b == 1 for b in by),
+        "converged_by_u_tau": sum(b == 2 for b in by),
         "capped": sum(s == L.LBM_SLOT_CAPPED for s in st),
         "diverged": sum(s == L.LBM_SLOT_DIVERGED for s in st),
         "lattice_updates": int(sum(r["steps"] * r["cells"] for r in results.values())),
@@ -70,7 +80,7 @@ def _summary(results: dict, makespan: float) -> dict:
 
 def run_batched(requests: list, pool_bytes: int, chunk: int = 200, tol: float = 1e-8,
                 max_steps: int = 20000, max_slots: int = 1024, keep_fields: set = frozenset(),
-                device="cuda:0", log=None) -> tuple:
+                device="cuda:0", log=None, tol_utau: float = 0.0) -> tuple:
     """Continuous batching in one pool.  Returns (results by id, summary)."""
     pool = L.Pool(pool_bytes, max_slots=max_slots, device=device)
     reqs = sorted(requests, key=lambda r: r["t_arrival"])
@@ -81,7 +91,7 @@ def run_batched(requests: list, pool_bytes: int, chunk: int = 200, tol: float = 
         now = time.perf_counter() - t0
         while i < len(reqs) and reqs[i]["t_arrival"] <= now:
             lat, nx, ny, nz, p, u0 = request_lattice(reqs[i])
-            slot = pool.lbm_pool_admit(lat, nx, ny, nz, p, u0, tol, max_steps)
+            slot = pool.lbm_pool_admit(lat, nx, ny, nz, p, u0, tol, max_steps, tol_utau=tol_utau)
             if slot is None:
                 break  # wait for memory / a slot to free up (arrival order is kept)
             active[slot] = (reqs[i], now)
@@ -100,6 +110,7 @@ def run_batched(requests: list, pool_bytes: int, chunk: int = 200, tol: float = 
             res = {"latency": now - req["t_arrival"], "queued": t_adm - req["t_arrival"],
                    "steps": st["steps"], "status": st["status"], "batched": st["batched"],
                    "residual": st["residual"], "mean_u_tau": st["mean_u_tau"],
+                   "d_u_tau_rel": st["d_u_tau_rel"], "converged_by": st["converged_by"],
                    "cells": req["nx"] * req["ny"]}
             if req["id"] in keep_fields:
                 v = pool.lbm_pool_lattice(slot)
@@ -120,8 +131,9 @@ def run_batched(requests: list, pool_bytes: int, chunk: int = 200, tol: float = 
 
 def run_sequential(requests: list, tol: float = 1e-8, max_steps: int = 20000, check_every: int = 100,
                    keep_fields: set = frozenset(), device="cuda:0", honor_arrivals: bool = True,
-                   log=None) -> tuple:
-    """The same requests one at a time through the plain per-lattice path."""
+                   log=None, tol_utau: float = 0.0) -> tuple:
+    """The same requests one at a time through the plain per-lattice path
+    (checks every `check_every` steps, the lattices' reduction period)."""
     reqs = sorted(requests, key=lambda r: r["t_arrival"])
     results = {}
     t0 = time.perf_counter()
@@ -131,21 +143,33 @@ def run_sequential(requests: list, tol: float = 1e-8, max_steps: int = 20000, ch
             time.sleep(req["t_arrival"] - now)
         lat, nx, ny, nz, p, u0 = request_lattice(req)
         g = L.Lattice(lat, nx, ny, nz, p, device=device)
-        status, steps, r = L.LBM_SLOT_CAPPED, 0, {}
+        status, steps, r, by = L.LBM_SLOT_CAPPED, 0, {}, 0
         while steps < max_steps:
             n = min(check_every, max_steps - steps)
-            g.lbm_step(n)
+            try:
+                g.lbm_step(n)
+            except L.LbmError as e:
+                if e.code != L.LBM_EDIVERGED:
+                    raise
+                status = L.LBM_SLOT_DIVERGED
+                break
             steps += n
             r = g.lbm_residual()
             if r["rc"] == L.LBM_EDIVERGED:
                 status = L.LBM_SLOT_DIVERGED
                 break
+            if steps % check_every:
+                continue  # only reduction steps decide convergence
             if r["l2_du_rel"] < tol:
-                status = L.LBM_SLOT_CONVERGED
+                status, by = L.LBM_SLOT_CONVERGED, 1
+                break
+            if tol_utau > 0 and 0 <= r["d_u_tau_rel"] < tol_utau:
+                status, by = L.LBM_SLOT_CONVERGED, 2
                 break
         res = {"latency": time.perf_counter() - t0 - req["t_arrival"], "steps": steps,
                "status": status, "batched": False, "residual": r.get("l2_du_rel"),
-               "mean_u_tau": r.get("mean_u_tau"), "cells": nx * ny}
+               "mean_u_tau": r.get("mean_u_tau"), "d_u_tau_rel": r.get("d_u_tau_rel"),
+               "converged_by": by, "cells": nx * ny}
         if req["id"] in keep_fields:
             res["u"] = g.lbm_moments()[1]
             res["utau"] = g.lbm_wall()["utau"]

@@ -558,3 +558,110 @@ def test_config2_full_size_plate_f64(scheme):
     o.step(40)
     g.lbm_step(40)
     _compare_f64(o, g, tol=1e-10)
+
+
+@pytest.mark.parametrize("q,nx,ny,nz", [(9, 4, 16, 1), (19, 256, 16, 3), (9, 384, 16, 1)])
+def test_fused_reduction_matches_oracle(q, nx, ny, nz):
+    """The reduction carried by the even channel step (reduce_every = 10:
+    steps 10 and 20, on a flat and on row-mapped lattices): mass, momentum,
+    mean u_tau and the residual ||u^20 - u^10|| / (10 ||u^20||) against the
+    oracle's fields."""
+    lat = units.channel(2000.0, 8)
+    u0 = _channel_u0(q, nx, ny, nz, lat["u_bulk"])
+    o, g = _pair(q, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"] * 10, 0, 0))
+    gp = L.lbm_params_default(precision=L.LBM_F64, scheme=L.LBM_WALL_SLIP_BB, nu=lat["nu"],
+                              force=(lat["force"] * 10, 0, 0), reduce_every=10)
+    g = L.Lattice(q, nx, ny, nz, gp)
+    g.lbm_set_velocity(u0)
+    o.step(10)
+    u10 = o.u().reshape(o.D, -1).copy()
+    o.step(10)
+    g.lbm_step(20)
+    r = g.lbm_residual()  # the step-20 reduction, not a new one
+    u20 = o.u().reshape(o.D, -1)
+    tot = o.totals()
+    assert r["step"] == 20 and r["steps_since_previous"] == 10 and r["nan_flag"] == 0.0
+    assert abs(r["mass"] - tot[0]) < 1e-12 * tot[0]
+    D = o.D
+    assert np.allclose(r["momentum"][:D], tot[1:1 + D], rtol=1e-11, atol=1e-16)
+    l2 = np.linalg.norm(u20 - u10) / (10 * np.linalg.norm(u20))
+    assert abs(r["l2_du_rel"] / l2 - 1) < 1e-9
+    ut = o.wall()["utau"]
+    assert abs(r["mean_u_tau"] / ut.mean() - 1) < 1e-12
+    assert r["d_u_tau_rel"] >= 0.0
+
+
+@pytest.mark.parametrize("flow,reduce_every", [("channel", 2), ("channel", 3), ("plate", 2)])
+def test_lbm_step_reports_divergence_by_itself(flow, reduce_every):
+    """A NaN in the start field: lbm_step's own periodic reductions (fused
+    in the channel's even steps, standalone otherwise) raise the divergence
+    flag, which a later lbm_step call returns as LBM_EDIVERGED without
+    lbm_residual ever being called."""
+    torch = _torch_gpu()
+    kw = dict(precision=L.LBM_F64, scheme=L.LBM_WALL_SLIP_BB, sa_on=1, nu=1e-3,
+              reduce_every=reduce_every)
+    nx, ny = (4, 16) if flow == "channel" else (40, 12)
+    if flow == "plate":
+        kw.update(flow=L.LBM_FLOW_PLATE, plate_start=6, u_inlet=0.05, collision=L.LBM_COLL_CM)
+    g = L.Lattice(9, nx, ny, 1, L.lbm_params_default(**kw))
+    u = np.full((2, 1, ny, nx), 0.01)
+    u[0, 0, 5, 2] = np.nan
+    g.lbm_set_velocity(u)
+    try:
+        g.lbm_step(6)  # may already see an earlier reduction's flag
+    except L.LbmError as e:
+        assert e.code == L.LBM_EDIVERGED
+    torch.cuda.synchronize()
+    with pytest.raises(L.LbmError) as ei:
+        g.lbm_step(1)
+    assert ei.value.code == L.LBM_EDIVERGED
+    # a healthy lattice with the same reductions keeps stepping
+    h = L.Lattice(9, nx, ny, 1, L.lbm_params_default(**kw))
+    h.lbm_set_velocity(np.full((2, 1, ny, nx), 0.01))
+    h.lbm_step(6)
+    torch.cuda.synchronize()
+    h.lbm_step(6)
+    assert h.steps == 12
+
+
+def _rel_l2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("q,nx,ny,nz,collision", [(19, 512, 16, 4, O.BGK), (19, 512, 16, 4, O.CM),
+                                                  (9, 768, 16, 1, O.BGK), (19, 768, 8, 2, O.BGK)])
+def test_row_map_multi_block_perturbed_f64(q, nx, ny, nz, collision):
+    """Rows spanning two or three 256-thread blocks (as at 512 x 256 x 256),
+    with a seeded +-1e-3 perturbation so that every column differs: the
+    staged odd step's pushes across block edges and the even step, element-
+    wise against the oracle after 1, 2 and 9 more steps (both parities):
+    u, nu_tilde, nu_t, u_tau, u_w and the populations."""
+    lat = units.channel(5000.0, ny // 2)
+    u0 = _channel_u0(q, nx, ny, nz, lat["u_bulk"], amp=1e-3, seed=11)
+    o, g = _pair(q, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"] * 10, 0, 0), collision=collision)
+    for n in (1, 1, 9):
+        o.step(n)
+        g.lbm_step(n)
+        _compare_f64(o, g)
+        assert np.abs(g.lbm_populations() - o.f()).max() < 1e-13
+
+
+@pytest.mark.parametrize("q,nx,ny,nz", [(19, 512, 16, 4), (9, 768, 16, 1)])
+def test_row_map_multi_block_perturbed_f32(q, nx, ny, nz):
+    """The same lattices with FP32 storage and arithmetic (the benchmark's
+    kernel instantiation) against the FP64 oracle: relative L2 of u, nu_tilde,
+    u_tau and the populations after 1, 2 and 30 more steps."""
+    lat = units.channel(5000.0, ny // 2)
+    u0 = _channel_u0(q, nx, ny, nz, lat["u_bulk"], amp=1e-3, seed=12)
+    o, g = _pair(q, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"] * 10, 0, 0), precision="f32")
+    for n in (1, 1, 30):
+        o.step(n)
+        g.lbm_step(n)
+        _, ug, _ = g.lbm_moments()
+        errs = (_rel_l2(ug, o.u()), _rel_l2(g.lbm_nu_tilde(), o.nt()),
+                _rel_l2(g.lbm_wall()["utau"], o.wall()["utau"]),
+                _rel_l2(g.lbm_populations(), o.f()))
+        assert max(errs) < 1e-5, errs

@@ -245,3 +245,70 @@ def test_converged_requests_stop():
     for r in res.values():
         assert r["status"] == L.LBM_SLOT_CONVERGED and r["steps"] % 100 == 0
         assert r["residual"] < 1e-4
+
+
+@pytest.mark.parametrize("kind,ny", [("channel", 64), ("plate", 40)])
+def test_diverging_request_is_evicted_others_unchanged(kind, ny):
+    """One request starts from a field with a NaN (small persistent group for
+    the channel, multi-lattice group for the plate): the pool reports it
+    diverged at its first reduction and it can be released, while the two
+    requests resident beside it end bitwise equal to their runs alone."""
+    _gpu()
+    reqs = [_req(0, kind, ny, 2000.0, "slip_bb"), _req(1, kind, ny, 3000.0, "hrfd"),
+            _req(2, kind, ny, 1500.0, "slip_bb")]
+    cap = 300
+
+    def admit(pool, r, poison):
+        lat, nx, ny_, nz, p, _ = serving.request_lattice(r)
+        u0 = None
+        if poison:
+            u0 = np.zeros((2, 1, ny_, nx))
+            u0[0] = p.u_init[0]
+            u0[0, 0, ny_ // 2, nx // 2] = np.nan
+        return pool.lbm_pool_admit(lat, nx, ny_, nz, p, u0, 0.0, cap)
+
+    def run(ids, poison_id=None):
+        pool = L.Pool(512 << 20, max_slots=8)
+        slots = {i: admit(pool, reqs[i], i == poison_id) for i in ids}
+        pool.lbm_pool_step(150)
+        out = {}
+        if poison_id is not None:
+            st = pool.lbm_pool_poll(slots[poison_id])
+            assert st["status"] == L.LBM_SLOT_DIVERGED and st["steps"] == 100, st
+            pool.lbm_pool_release(slots[poison_id])
+        pool.lbm_pool_step(200)
+        for i in ids:
+            if i == poison_id:
+                continue
+            st = pool.lbm_pool_poll(slots[i])
+            assert st["status"] == L.LBM_SLOT_CAPPED and st["steps"] == cap
+            out[i] = (pool.lbm_pool_lattice(slots[i]).lbm_moments()[1], st["mean_u_tau"],
+                      st["batched"])
+        pool.close()
+        return out
+
+    mixed = run([0, 1, 2], poison_id=1)
+    assert mixed[0][2] == (kind == "channel")
+    for i in (0, 2):
+        alone = run([i])[i]
+        assert np.array_equal(alone[0], mixed[i][0]) and alone[1] == mixed[i][1], i
+
+
+def test_u_tau_criterion_batched_and_sequential():
+    """The paper's criterion (relative change of u_tau between reductions
+    below tol_utau, Sec. 4.1.1) retires requests at a reduction step; the
+    batched pool and the one-at-a-time path stop the same requests at the same
+    step and say which criterion fired."""
+    _gpu()
+    reqs = [_req(i, k, ny, rt, s) for i, (k, ny, rt, s) in
+            enumerate([("channel", 32, 800.0, "slip_bb"), ("channel", 48, 3000.0, "hrfd"),
+                       ("plate", 24, 1000.0, "slip_bb"), ("channel", 300, 5000.0, "slip_bb")])]
+    kw = dict(tol=0.0, tol_utau=1e-4, max_steps=20000)
+    rb, sb = serving.run_batched(reqs, 512 << 20, chunk=300, **kw)
+    rs, ss = serving.run_sequential(reqs, honor_arrivals=False, **kw)
+    assert sb["converged_by_u_tau"] >= 1 and sb["converged_by_residual"] == 0
+    for r in reqs:
+        b, q = rb[r["id"]], rs[r["id"]]
+        assert (b["status"], b["steps"], b["converged_by"]) == (q["status"], q["steps"], q["converged_by"]), r
+        if b["status"] == L.LBM_SLOT_CONVERGED:
+            assert b["steps"] % 100 == 0 and 0 <= b["d_u_tau_rel"] < 1e-4

@@ -25,7 +25,9 @@ def test_timing_counts_every_launch(calls):
     p = L.lbm_params_default(precision=L.LBM_F32, scheme=L.LBM_WALL_SLIP_BB, nu=lat["nu"],
                              force=(lat["force"], 0, 0), u_ref=lat["u_bulk"], reduce_every=2)
     g = L.Lattice(L.LBM_D3Q19, nx, ny, nz, p, device="cuda:0")
-    g.lbm_set_velocity(inputs.channel_velocity(0, 3, nz, ny, nx, lat["u_bulk"], 1e-3))
+    # the unperturbed bulk-velocity start: a perturbed BGK channel at this
+    # tau - 1/2 diverges within the 4100 steps (and lbm_step says so)
+    g.lbm_set_velocity(inputs.channel_velocity(0, 3, nz, ny, nx, lat["u_bulk"], 0.0))
     g.lbm_step(2)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
@@ -50,3 +52,25 @@ def test_timing_counts_every_launch(calls):
     assert t2["step_launches"] == 0 and t2["wall_launches"] == 0
     g.lbm_set_timing(False)
     assert g.steps == 2 + total + 3
+
+
+def test_sampled_timing_counts():
+    """lbm_set_timing(every = 10) times the launches of the two steps that
+    start at a multiple of 10 (both parities), and nothing else."""
+    _gpu()
+    import torch
+    nx, ny, nz = 64, 32, 8
+    lat = units.channel(2000.0, ny // 2, 0.05)
+    p = L.lbm_params_default(precision=L.LBM_F32, scheme=L.LBM_WALL_SLIP_BB, nu=lat["nu"],
+                             force=(lat["force"], 0, 0), reduce_every=5)
+    g = L.Lattice(L.LBM_D3Q19, nx, ny, nz, p, device="cuda:0")
+    g.lbm_step(3)
+    g.lbm_set_timing(True, every=10)
+    g.lbm_step(17)
+    g.lbm_step(25)   # steps 3 .. 44
+    torch.cuda.synchronize()
+    tm = g.lbm_get_timing()
+    g.lbm_set_timing(False)
+    timed = sum(1 for s in range(3, 45) if s % 10 < 2)
+    assert tm["step_launches"] == timed and tm["wall_launches"] == timed
+    assert tm["step_ms"] > 0
