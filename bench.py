@@ -12,18 +12,26 @@ steps, the FP64 residual reduction.
 --calibrate-copy times a plain device-to-device copy of known size instead;
 its hardware byte counters give the scale factor for the kernel's counters.
 
---serving runs the serving workload instead: seeded Poisson arrivals of 2-D
-channel and flat-plate solves (70/30, log-uniform Ny in [32, 1024] and Re_tau
-in [500, 20000], wall scheme drawn per request), each run to an L2 velocity
-residual below 1e-8 or to the step cap, through the batched pool and then one
-at a time through the plain per-lattice path; it prints solves/s and p50/p99
-time-to-result for both.
+The default run also measures the serving half of the metric on a bounded
+sample (the first 64 requests of the seeded serving workload, step cap 5000;
+--serving-requests, --serving-cap): seeded Poisson arrivals of 2-D channel
+and flat-plate solves (70/30, log-uniform Ny in [32, 1024] and Re_tau in
+[500, 20000], wall scheme drawn per request), each retired on an L2 velocity
+residual below 1e-8, on a relative change of the mean u_tau below 1e-4
+between reductions (Sec. 4.1.1), on divergence or at the cap, through the
+batched pool and then one at a time through the plain per-lattice path:
+solves/s, p50/p99 time-to-result and time-to-converged, and the same-result
+check.  --serving runs the whole 512-request workload alone instead.
+
+Kernel durations come from HIP events around the launches of two steps in
+every ten inside the timed region (both step parities), so the timed steps
+run back to back.
 
 Prints one JSON line: the metric, its value and unit, the timing contract
 fields, the workload, the roofline of the fused step kernel (algorithmic bytes
 per launch over its measured duration, against 8 TB/s, and the HBM traffic
-measured by the hardware counters when available) and the oracle's rate on
-the host for scale.
+measured by the hardware counters when available), the serving figures and
+the oracle's rate on the host's cores, one thread and all of them.
 """
 import argparse
 import json
@@ -53,13 +61,21 @@ def bytes_per_lup(q: int, precision: str, sa: bool = True) -> int:
     return 2 * q * sb + 2 * tb + 2 * D * tb
 
 
-def cpu_baseline(nx: int, ny: int, nz: int, lat: dict, steps: int, collision: str,
-                 amp: float) -> dict:
-    import numpy as np
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def _oracle_rate(nx, ny, nz, lat, steps, collision, amp, threads):
     import oracle as O
     from paper_2506_03905_amd import inputs
 
+    O.set_threads(threads)
     u0 = inputs.channel_velocity(0, 3, nz, ny, nx, lat["u_bulk"], amp)
     p = O.params(q=19, nx=nx, ny=ny, nz=nz, nu=lat["nu"], force=(lat["force"], 0, 0),
                  scheme=O.BB_SLIP, collision={"bgk": O.BGK, "cm": O.CM}[collision])
@@ -67,11 +83,26 @@ def cpu_baseline(nx: int, ny: int, nz: int, lat: dict, steps: int, collision: st
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
-    del o, u0
-    _ = np
-    return {"value": nx * ny * nz * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{nx}x{ny}x{nz} slab of the same channel (same resolution, Re_tau, start), "
-                      f"{steps} steps, FP64, 1 thread, {dt:.1f} s"}
+    return nx * ny * nz * steps / dt / 1e6, dt
+
+
+def cpu_baseline(nx: int, ny: int, lat: dict, steps: int, collision: str, amp: float) -> dict:
+    """The oracle on slabs of the same channel (same resolution, Re_tau and
+    start; full x and y extent, a few z planes): one thread, then every
+    thread the host gives it (OpenMP over lattice rows)."""
+    import oracle as O
+
+    threads = O.get_threads()  # OMP_NUM_THREADS or all cores
+    v1, dt1 = _oracle_rate(nx, ny, 4, lat, steps, collision, amp, 1)
+    nz_all = 4 * max(1, min(threads, 16))
+    vn, dtn = _oracle_rate(nx, ny, nz_all, lat, steps, collision, amp, threads)
+    O.set_threads(threads)
+    return {"value": round(vn, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle on a {nx}x{ny}x{nz_all} slab of the same channel (same "
+                      f"resolution, Re_tau, start), {steps} steps, {threads} threads, {dtn:.1f} s",
+            "one_thread": {"value": round(v1, 3), "unit": "MLUPS",
+                           "sample": f"{nx}x{ny}x4 slab, {steps} steps, 1 thread, {dt1:.1f} s"},
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 def timed_steps(g, steps: int, warmup: int):
@@ -180,6 +211,43 @@ def serving_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def serving_sample(n_requests: int, cap: int, rate: float, chunk: int, tol: float,
+                   tol_utau: float) -> dict:
+    """The serving half of the metric on the first n_requests of the seeded
+    workload: batched pool vs the same requests one at a time."""
+    import torch
+
+    from paper_2506_03905_amd import inputs, serving
+
+    reqs = inputs.requests(0, n_requests, rate)
+    need = sum(serving.footprint(r) for r in reqs)
+    pool_bytes = min(int(need * 1.05) + (64 << 20), 64 << 30)
+    kw = dict(tol=tol, tol_utau=tol_utau, max_steps=cap)
+    res_b, sum_b = serving.run_batched(reqs, pool_bytes, chunk=chunk, **kw)
+    torch.cuda.synchronize()
+    res_s, sum_s = serving.run_sequential(reqs, **kw)
+    same = [res_b[r["id"]]["status"] == res_s[r["id"]]["status"] and
+            res_b[r["id"]]["steps"] == res_s[r["id"]]["steps"] and
+            res_b[r["id"]]["converged_by"] == res_s[r["id"]]["converged_by"] for r in reqs]
+    dut = [abs(res_b[r["id"]]["mean_u_tau"] - res_s[r["id"]]["mean_u_tau"]) /
+           max(abs(res_s[r["id"]]["mean_u_tau"]), 1e-300) for r in reqs
+           if res_s[r["id"]]["status"] != 4 and res_b[r["id"]]["status"] != 4]
+    keep = ("solves_per_s", "makespan_s", "p50_s", "p99_s", "p50_converged_s", "p99_converged_s",
+            "converged", "converged_by_residual", "converged_by_u_tau", "capped", "diverged",
+            "lattice_updates")
+    return {"workload": f"first {n_requests} requests of the serving workload (Poisson "
+                        f"{rate:g}/s, 70% channel 4 x Ny / 30% plate 8Ny x Ny, Ny in [32, 1024], "
+                        f"Re_tau in [500, 20000]), D2Q9 FP32 CM + SA, retired on residual < "
+                        f"{tol:g} or d(u_tau)/u_tau < {tol_utau:g} per 100 steps, cap {cap} steps",
+            "unit": "solves/s",
+            "batched": {k: sum_b[k] for k in keep},
+            "sequential": {k: sum_s[k] for k in keep},
+            "speedup_solves_per_s": sum_b["solves_per_s"] / sum_s["solves_per_s"]
+                                    if sum_s["solves_per_s"] > 0 else None,
+            "same_steps_status_criterion": f"{sum(same)}/{len(same)}",
+            "max_rel_diff_mean_u_tau": max(dut) if dut else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,7 +261,7 @@ def main():
     ap.add_argument("--ny", type=int, default=None)
     ap.add_argument("--nz", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--collision", default="bgk", choices=["bgk", "cm"])
     ap.add_argument("--amp", type=float, default=0.0)
     ap.add_argument("--sa", default="on", choices=["on", "off"])
@@ -206,13 +274,18 @@ def main():
     ap.add_argument("--chunk", type=int, default=200)
     ap.add_argument("--seq-requests", type=int, default=-1,
                     help="requests run sequentially (default: all)")
+    ap.add_argument("--tol-utau", type=float, default=1e-4)
+    ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--serving-cap", type=int, default=5000)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--timing-every", type=int, default=10,
+                    help="kernel events around 2 steps in every k (1: every launch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the lattice is not sharded across GPUs here "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.calibrate_copy:
@@ -254,7 +327,7 @@ def main():
           f"tau-1/2={3 * lat['nu']:.3e}, footprint {g.bytes / 1e9:.2f} GB", file=sys.stderr, flush=True)
     g.lbm_step(args.warmup)
     torch.cuda.synchronize()
-    g.lbm_set_timing(True)
+    g.lbm_set_timing(True, every=args.timing_every)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -280,7 +353,7 @@ def main():
         t = profile_summary.read_traffic(os.path.join(ROOT, "profiles", TRAFFIC_PROFILE))
         traffic = None if t is None else round(t["traffic_bytes"])
     out = {
-        "metric": "MLUPS & % HBM peak (D3Q19 fp32)",
+        "metric": "MLUPS & % HBM peak (D3Q19 fp32); batched solves/s + p99 latency vs plain",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -304,6 +377,7 @@ def main():
                      "kernel": "k_step", "bytes_per_lup": bpl,
                      "algorithmic_bytes_per_launch": bpl * ncell,
                      "kernel_ms": round(k_ms, 4),
+                     "kernel_launches_timed": tm["step_launches"],
                      # HBM bytes the counters measured per launch over the launch time
                      "measured_gbs": None if traffic is None else round(traffic / (k_ms * 1e-3) / 1e9, 1),
                      # the populations alone (read and written once), the figure LBM codes quote
@@ -314,11 +388,16 @@ def main():
                      "nan_flag": res["nan_flag"]},
         "host_wall_s": round(wall_s, 3),
     }
+    del g
+    torch.cuda.synchronize()
+    if not args.no_serving:
+        print(f"# serving sample: {args.serving_requests} requests, cap {args.serving_cap}",
+              file=sys.stderr, flush=True)
+        out["serving"] = serving_sample(args.serving_requests, args.serving_cap, args.rate,
+                                        args.chunk, args.tol, args.tol_utau)
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(nx, ny, 4, lat, args.cpu_steps, args.collision,
-                                           args.amp)
-    _ = np
+        out["cpu_baseline"] = cpu_baseline(nx, ny, lat, args.cpu_steps, args.collision, args.amp)
     print(json.dumps(out), flush=True)
 
 

@@ -94,7 +94,7 @@ def lib() -> ctypes.CDLL:
         raise RuntimeError(f"{LIB_PATH} is missing: build it first "
                            "(python -m paper_2506_03905_amd.build)")
     L = ctypes.CDLL(LIB_PATH)
-    vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
     P = ctypes.POINTER(lbm_params_t)
     sig = {
         "lbm_params_default": (None, [P]),
@@ -136,7 +136,6 @@ def lib() -> ctypes.CDLL:
         fn = getattr(L, name)
         fn.restype = res
         fn.argtypes = args
-    _ = dp
     _lib = L
     return L
 

@@ -25,7 +25,6 @@ import json
 import sys
 import time
 
-import numpy as np
 
 from . import lbm as L
 from . import units
@@ -128,7 +127,6 @@ def main(argv=None):
     rows = run(cases(a.studies.split(",")), tol=a.tol, max_steps=a.max_steps,
                log=lambda m: print("# " + m, file=sys.stderr, flush=True))
     print(json.dumps(rows) if a.json else table(rows), flush=True)
-    _ = np
 
 
 if __name__ == "__main__":
