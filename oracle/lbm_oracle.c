@@ -35,9 +35,11 @@
 #include <omp.h>
 #endif
 
-/* Threads: the per-cell loops are shared out by rows (OpenMP).  Every cell's
- * arithmetic is the same whatever thread runs it, and no loop sums across
- * cells, so any thread count gives bitwise the same result. */
+/* Threads: the per-cell loops are shared out by rows (OpenMP) on lattices of
+ * at least ORC_PAR_MIN cells.  Every cell's arithmetic is the same whatever
+ * thread runs it, and no loop sums across cells, so any thread count gives
+ * bitwise the same result. */
+#define ORC_PAR_MIN 16384
 void orc_set_threads(int n)
 {
 #ifdef _OPENMP
@@ -460,7 +462,7 @@ static void wall_function(orc *o, double *nt_out)
 {
     const orc_params *p = &o->p;
     const double yB = p->wall_dist, yF = 1.0 + p->wall_dist; /* Sec. 3.1: B and F */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (o->nwall >= ORC_PAR_MIN / 16)
     for (int64_t w = 0; w < o->nwall; ++w) {
         double n[3] = {0.0, (double)o->wside[w], 0.0};
         double uF[3], uB[3];
@@ -612,7 +614,7 @@ static void interpolated_bounce_back(orc *o, int outlet)
     const int Q = p->q;
     const int64_t N = o->ncell;
     const double q = p->wall_dist;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (o->nwall >= ORC_PAR_MIN / 16)
     for (int64_t w = 0; w < o->nwall; ++w) {
         const int64_t cell = o->wB[w];
         const int side = o->wside[w];
@@ -653,7 +655,7 @@ static void stream(orc *o)
     const orc_params *p = &o->p;
     const int Q = p->q, nx = p->nx, ny = p->ny, nz = p->nz;
     const int64_t N = o->ncell;
-#pragma omp parallel for collapse(2) schedule(static)
+#pragma omp parallel for collapse(2) schedule(static) if (o->ncell >= ORC_PAR_MIN)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -699,14 +701,14 @@ static void stream(orc *o)
     if (p->flow == ORC_PLATE) {
         /* outlet: the unknown populations are copied from the streamed
          * populations of the column x = nx - 2 */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (o->ncell >= ORC_PAR_MIN)
         for (int y = 0; y < ny; ++y) {
             int64_t c1 = cidx(o, nx - 1, y, 0), c2 = cidx(o, nx - 2, y, 0);
             for (int i = 0; i < Q; ++i)
                 if (o->c[3 * i] < 0) o->fnew[i * N + c1] = o->fnew[i * N + c2];
         }
         /* inlet: Zou-He with u = (u_inlet, 0) */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (o->ncell >= ORC_PAR_MIN)
         for (int y = 0; y < ny; ++y) {
             int64_t c0 = cidx(o, 0, y, 0);
             double f[9];
@@ -778,10 +780,10 @@ static void hrfd(orc *o)
     const int64_t N = o->ncell;
     const double yB = 0.5;
     double *ubx = (double *)malloc((o->nwall + 1) * sizeof(double));
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (o->nwall >= ORC_PAR_MIN / 16)
     for (int64_t w = 0; w < o->nwall; ++w)
         ubx[w] = o->utau[w] * orc_uplus(p->law, yB * o->utau[w] / p->nu, p->kappa, p->B) * o->tdir[3 * w];
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (o->nwall >= ORC_PAR_MIN / 16)
     for (int64_t w = 0; w < o->nwall; ++w) {
         int64_t cell = o->wB[w];
         const double *t = &o->tdir[3 * w];
@@ -823,7 +825,7 @@ static void collide_and_sa(orc *o)
     const orc_params *p = &o->p;
     const int Q = p->q, D = o->D, nx = p->nx, ny = p->ny, nz = p->nz;
     const int64_t N = o->ncell;
-#pragma omp parallel for collapse(2) schedule(static)
+#pragma omp parallel for collapse(2) schedule(static) if (o->ncell >= ORC_PAR_MIN)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -846,7 +848,7 @@ static void collide_and_sa(orc *o)
         return;
     }
     /* SA update from nu_tilde^n and the previous step's velocity */
-#pragma omp parallel for collapse(2) schedule(static)
+#pragma omp parallel for collapse(2) schedule(static) if (o->ncell >= ORC_PAR_MIN)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {

@@ -444,29 +444,48 @@ __device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S 
         const T uvec[3] = {ux, uy, uz}, Fv[3] = {Fx, Fy, Fz};
         cm_collide<Q, T>(f, drho, rho, uvec, Fv, omega);
     } else {
-        // BGK with Guo forcing, f* = (1 - omega) f + omega f_eq + S with
+        // BGK with Guo forcing, f* = f - omega (f - f_eq) + S with
         //   f_eq_i = w_i (drho + rho (3 cu + 9/2 cu^2 - 3/2 u.u))      (deviation form)
         //   S_i    = (1 - omega/2) w_i (3 (c_i.F - u.F) + 9 cu (c_i.F)),  cu = c_i.u
         // taken per pair (i, opp(i)): the parts even in c_i are shared by the
-        // pair, the odd parts change sign.
+        // pair, the odd parts change sign.  The relaxation acts on f - f_eq:
+        // written as (1 - omega) f + omega f_eq, the rounding of 1 - omega
+        // (omega near 2) leaves (1 - omega) + omega != 1 in the momentum sum, a
+        // bias of ulp(1) * rho u per step that the FP32 path accumulated to
+        // 1e-4 of u within 1000 steps (the body force is ~1e-8 per step).
         const T uu = ux * ux + uy * uy + uz * uz;
-        const T om1 = (T)1 - omega;
         const T fpref = (T)1 - (T)0.5 * omega;
         const T uF = ux * Fx + uy * Fy + uz * Fz;
-        // per unit weight: the c-independent part of omega f_eq + S
-        const T s0 = omega * (drho - (T)1.5 * rho * uu) - (T)3 * fpref * uF;
-        const T q45 = omega * (T)4.5 * rho, q3 = omega * (T)3 * rho;
-        const T f9 = (T)9 * fpref, f3 = (T)3 * fpref;
-        f[0] = om1 * f[0] + (T)wgt<Q>(0) * s0;
+        // r = rho u - (j + F/2): the first moment the equilibrium carries minus
+        // the one eq. 5 gives it, exact to the rounding of a small number.  The
+        // half-force shift is a few ulp of j in FP32, so the rounding of u is
+        // the same at every step and would bias the momentum input by up to a
+        // tenth of the body force per step; the source removes omega r.
+        const T rx = fma(rho, ux, -jx) - (T)0.5 * Fx, ry = fma(rho, uy, -jy) - (T)0.5 * Fy;
+        const T rz = D == 3 ? fma(rho, uz, -jz) - (T)0.5 * Fz : (T)0;
+        // odd part of the source per unit weight: 3 c_i . G, G = (1 - omega/2) F - omega r
+        const T Gx = (T)3 * (fpref * Fx - omega * rx), Gy = (T)3 * (fpref * Fy - omega * ry);
+        const T Gz = (T)3 * (fpref * Fz - omega * rz);
+        // per unit weight: the c-independent parts of f_eq and of S
+        const T e0 = drho - (T)1.5 * rho * uu;
+        const T s0 = (T)-3 * fpref * uF;
+        const T r45 = (T)4.5 * rho, r3 = (T)3 * rho;
+        const T f9 = (T)9 * fpref;
+        {
+            const T w0 = (T)wgt<Q>(0);
+            f[0] = (f[0] - omega * (f[0] - w0 * e0)) + w0 * s0;
+        }
         sfor<(Q - 1) / 2>([&](auto kc) {
             constexpr int i = 2 * decltype(kc)::value + 1, io = opp<Q>(i);
             static_assert(io == i + 1, "pairs (2k+1, 2k+2)");
             const T w = (T)wgt<Q>(i);
             const T cu = (T)cx<Q>(i) * ux + (T)cy<Q>(i) * uy + (T)cz<Q>(i) * uz;
-            const T even = w * s0 + (w * q45) * (cu * cu) + (f9 * K.cf[i]) * cu;
-            const T odd = (w * q3) * cu + f3 * K.cf[i];
-            f[i] = om1 * f[i] + (even + odd);
-            f[io] = om1 * f[io] + (even - odd);
+            const T E = w * (e0 + r45 * (cu * cu)), O = (w * r3) * cu;   // f_eq = E +- O
+            const T Se = w * s0 + (f9 * K.cf[i]) * cu;                     // S = Se +- So
+            const T So = w * ((T)cx<Q>(i) * Gx + (T)cy<Q>(i) * Gy + (T)cz<Q>(i) * Gz);
+            const T ti = f[i] - (E + O), tio = f[io] - (E - O);
+            f[i] = (f[i] - omega * ti) + (Se + So);
+            f[io] = (f[io] - omega * tio) + (Se - So);
         });
     }
     // post-collision populations of a wall cell for its interpolated links

@@ -93,6 +93,11 @@ def lib() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it first "
                            "(python -m paper_2506_03905_amd.build)")
+    # torch ships its own HIP runtime with the same soname as the system one
+    # the library links; the process must use one runtime for both (torch's
+    # streams and buffers are handed to the library), and it works when
+    # torch's is loaded first, so load torch before the library.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i64 = ctypes.c_void_p, ctypes.c_int64
     P = ctypes.POINTER(lbm_params_t)
