@@ -264,6 +264,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--collision", default="bgk", choices=["bgk", "cm"])
     ap.add_argument("--amp", type=float, default=0.0)
+    ap.add_argument("--store-shift", type=float, default=0.0,
+                    help="store f - f_eq(rho0, (s U_b, 0, 0)) (s = this value; 0 stores f - w rho0)")
     ap.add_argument("--sa", default="on", choices=["on", "off"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB")
     ap.add_argument("--serving", action="store_true")
@@ -318,7 +320,8 @@ def main():
     coll = {"bgk": L.LBM_COLL_BGK, "cm": L.LBM_COLL_CM}[args.collision]
     p = L.lbm_params_default(precision=L.PRECISION[args.precision], scheme=L.LBM_WALL_SLIP_BB,
                              nu=lat["nu"], force=(lat["force"], 0, 0), u_ref=lat["u_bulk"],
-                             reduce_every=100, collision=coll, sa_on=1 if args.sa == "on" else 0)
+                             reduce_every=100, collision=coll, sa_on=1 if args.sa == "on" else 0,
+                             store_shift_u=args.store_shift * lat["u_bulk"])
     g = L.Lattice(L.LBM_D3Q19, nx, ny, nz, p, device="cuda:0")
     u0 = inputs.channel_velocity(0, 3, nz, ny, nx, lat["u_bulk"], args.amp)
     g.lbm_set_velocity(u0)
@@ -327,7 +330,9 @@ def main():
           f"tau-1/2={3 * lat['nu']:.3e}, footprint {g.bytes / 1e9:.2f} GB", file=sys.stderr, flush=True)
     g.lbm_step(args.warmup)
     torch.cuda.synchronize()
-    g.lbm_set_timing(True, every=args.timing_every)
+    # sampled events need a window of several periods; short runs time every launch
+    every = args.timing_every if args.steps >= 2 * args.timing_every else 1
+    g.lbm_set_timing(True, every=every)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -347,8 +352,8 @@ def main():
     k_ms = tm["step_ms"] / max(tm["step_launches"], 1)
     achieved = bpl * ncell / (k_ms * 1e-3) / 1e9
     traffic = None
-    if (nx, ny, nz, args.precision, args.collision, args.sa, args.amp) == \
-            (512, 256, 256, "f32", "bgk", "on", 0.0):
+    if (nx, ny, nz, args.precision, args.collision, args.sa, args.amp, args.store_shift) == \
+            (512, 256, 256, "f32", "bgk", "on", 0.0, 0.0):
         from paper_2506_03905_amd import profile_summary
         t = profile_summary.read_traffic(os.path.join(ROOT, "profiles", TRAFFIC_PROFILE))
         traffic = None if t is None else round(t["traffic_bytes"])
@@ -370,7 +375,9 @@ def main():
                                f"{args.collision.upper()}" + (" + SA" if args.sa == "on" else
                                                                " (no SA)") + ", slip-velocity bounce-back "
                                f"(Reichardt), Dean start" + (f" + {args.amp:g} perturbation"
-                                                             if args.amp else ""),
+                                                             if args.amp else "")
+                               + (f", stored f - f_eq(rho0, {args.store_shift:g} U_b)" if args.store_shift
+                                  else ""),
                    "cells": ncell, "collision": args.collision, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,

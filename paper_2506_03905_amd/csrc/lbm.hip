@@ -61,6 +61,7 @@ constexpr int BLK = 256;  // threads per block of the per-cell kernels (128 and 
 #endif
 constexpr int NRED = 8;        // reduction slots
 constexpr int RED_BLOCKS = 2048;
+constexpr int MID_BLOCKS = 256;  // blocks of the middle pass of a reduction
 constexpr int RES_STICKY = 2 * NRED;  // result[RES_STICKY]: 1 once any reduction saw a bad cell
 
 // ---------------------------------------------------------------------------
@@ -958,17 +959,33 @@ template <int Q, typename S, typename T> __global__ void __launch_bounds__(BLK) 
     reduce_part<Q, S, T>(P, odd_state, cur, blockIdx.x, gridDim.x);
 }
 
-// Second pass of a lattice's reduction: slots 0-6 from the nblocks partials
-// (written by k_reduce or by a fused k_step), slot 7 from the wall cells'
-// u_tau; result slot `slot` gets the sums, and the sticky divergence flag
-// P.result[RES_STICKY] is raised when this reduction saw a bad cell.
-__global__ void __launch_bounds__(BLK) k_reduce_final(KP P, int nblocks, int slot)
+// Middle pass of a lattice's reduction: block b of MID_BLOCKS sums its fixed
+// slice of the nrows partial rows (slots 0-6, written by k_reduce or by a
+// fused k_step) and of the wall cells' u_tau (slot 7) into P.mid[b].
+__global__ void __launch_bounds__(BLK) k_reduce_mid(KP P, int64_t nrows)
 {
     __shared__ double sh[8][BLK];
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t b = threadIdx.x; b < nblocks; b += BLK)
-        for (int k = 0; k < 7; ++k) acc[k] += P.partials[b * NRED + k];
-    for (int64_t w = threadIdx.x; w < P.nwall; w += BLK) acc[7] += P.utau[w];
+    const int64_t b = blockIdx.x;
+    const int64_t rper = (nrows + MID_BLOCKS - 1) / MID_BLOCKS, wper = (P.nwall + MID_BLOCKS - 1) / MID_BLOCKS;
+    const int64_t r1 = std::min(nrows, (b + 1) * rper), w1 = std::min(P.nwall, (b + 1) * wper);
+    for (int64_t r = b * rper + threadIdx.x; r < r1; r += BLK)
+        for (int k = 0; k < 7; ++k) acc[k] += P.partials[r * NRED + k];
+    for (int64_t w = b * wper + threadIdx.x; w < w1; w += BLK) acc[7] += P.utau[w];
+    block_sum<BLK>(sh, acc, 8);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 8; ++k) P.mid[b * NRED + k] = sh[k][0];
+}
+
+// Last pass: the MID_BLOCKS rows of P.mid into result slot `slot`; the sticky
+// divergence flag P.result[RES_STICKY] is raised when this reduction saw a
+// bad cell.
+__global__ void __launch_bounds__(BLK) k_reduce_final(KP P, int slot)
+{
+    __shared__ double sh[8][BLK];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < MID_BLOCKS; b += BLK)
+        for (int k = 0; k < 8; ++k) acc[k] += P.mid[b * NRED + k];
     block_sum<BLK>(sh, acc, 8);
     if (threadIdx.x == 0) {
         for (int k = 0; k < 8; ++k) P.result[slot * NRED + k] = sh[k][0];
@@ -1283,7 +1300,7 @@ int storage_bytes(int precision)
 }
 
 struct Layout {
-    int64_t pops, u0, u1, nt0, nt1, usnap, utau, tdir, uw, wrho, ubwf, gan, partials, result, ibuf, total;
+    int64_t pops, u0, u1, nt0, nt1, usnap, utau, tdir, uw, wrho, ubwf, gan, partials, result, mid, ibuf, total;
 };
 
 int64_t nwall_of(int flow, int nx, int nz, int plate_start)
@@ -1319,6 +1336,7 @@ bool make_layout(int Q, int nx, int ny, int nz, const lbm_params_t *p, Layout *L
     const int64_t step_blocks = std::max((int64_t)ny * nz * ((nx + BLK - 1) / BLK), (N + BLK - 1) / BLK);
     L->partials = o; o = align256(o + std::max((int64_t)RED_BLOCKS, step_blocks) * NRED * 8);
     L->result = o; o = align256(o + 32 * 8);
+    L->mid = o; o = align256(o + (int64_t)MID_BLOCKS * NRED * 8);
     L->ibuf = o; o = align256(o + (p->bb_interp != LBM_IBB_HALFWAY ? (int64_t)Q * nw * 8 : 0));
     L->total = o;
     return true;
@@ -1438,7 +1456,9 @@ template <int Q, typename S, typename T> struct Impl {
             hipLaunchKernelGGL((k_reduce<Q, S, T>), dim3((unsigned)nb), dim3(BLK), 0, h->stream, h->kp, odd_state, cur);
             HIPCHK(hipGetLastError());
         }
-        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLK), 0, h->stream, h->kp, (int)nb, slot);
+        hipLaunchKernelGGL(k_reduce_mid, dim3(MID_BLOCKS), dim3(BLK), 0, h->stream, h->kp, nb);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLK), 0, h->stream, h->kp, slot);
         HIPCHK(hipGetLastError());
         return LBM_OK;
     }
@@ -1597,6 +1617,7 @@ void fill_kp(lbm *h)
     k.bb_interp = p.bb_interp;
     k.wall_dist = p.wall_dist;
     k.result = (double *)(b + L.result);
+    k.mid = (double *)(b + L.mid);
     fill_cellk(k, h->Q, k.kd);
     fill_cellk(k, h->Q, k.kf);
 }

@@ -174,6 +174,7 @@ struct KP {
     double *gan;         // nwall: analytic wall-normal gradient (u_tau^2/nu) du+/dy+ at B
     double *partials;    // reduction partials
     double *result;      // reduction result slots
+    double *mid;         // reduction middle-pass rows
     double *ibuf;        // Q * nwall: post-collision populations of the wall cells (interpolated links)
     double wall_dist;    // distance of the first node from the wall (1/2: halfway)
     int bb_interp;       // IBB_HALFWAY / IBB_BOUZIDI / IBB_YU

@@ -77,7 +77,9 @@ def lattice_of(case: dict):
 
 
 def run(case_list: list, tol: float = 1e-9, max_steps: int = 600000, chunk: int = 2000,
-        log=None) -> list:
+        log=None, keep_fields: bool = False) -> list:
+    """Runs every case to convergence (residual below tol) or max_steps in one
+    pool; keep_fields adds each case's final velocity field and u_tau."""
     pool = L.Pool(1 << 30, max_slots=max(len(case_list), 1))
     slots = []
     for c in case_list:
@@ -99,7 +101,8 @@ def run(case_list: list, tol: float = 1e-9, max_steps: int = 600000, chunk: int 
         _, u, _ = v.lbm_moments()
         ub = float(u[0].mean())
         ut = float(v.lbm_wall()["utau"].mean())
-        rows.append({**c, "ny": ny, "steps": s["steps"],
+        extra = {"u": u, "utau": v.lbm_wall()["utau"]} if keep_fields else {}
+        rows.append({**c, **extra, "ny": ny, "steps": s["steps"],
                      "status": {2: "converged", 3: "capped", 4: "diverged"}.get(s["status"], "?"),
                      "residual": s["residual"], "u_tau/target": ut / u_tau,
                      "U_b/dean": ub / u_b, "cf_b/dean": (ut / ub) ** 2 / (u_tau / u_b) ** 2,
@@ -123,10 +126,22 @@ def main(argv=None):
     ap.add_argument("--max-steps", type=int, default=600000)
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--json", action="store_true")
+    ap.add_argument("--out", default=None, help="also write the table (markdown) to this file")
     a = ap.parse_args(argv)
+    t0 = time.perf_counter()
     rows = run(cases(a.studies.split(",")), tol=a.tol, max_steps=a.max_steps,
                log=lambda m: print("# " + m, file=sys.stderr, flush=True))
-    print(json.dumps(rows) if a.json else table(rows), flush=True)
+    text = json.dumps(rows) if a.json else table(rows)
+    print(text, flush=True)
+    if a.out:
+        with open(a.out, "w") as fh:
+            fh.write("# Channel studies of Sec. 4.1 (written by paper_2506_03905_amd.replicate)\n\n"
+                     f"Command: `python -m paper_2506_03905_amd.replicate --studies {a.studies} "
+                     f"--max-steps {a.max_steps} --tol {a.tol:g} --out {a.out}`; "
+                     f"{len(rows)} channels in one serving pool, {time.perf_counter() - t0:.1f} s on one "
+                     "MI355X.  D2Q9 4 x 2N, FP64, central-moment collision + SA, Dean start; "
+                     "u_tau/target = the wall function's mean friction velocity over the one the "
+                     "body force imposes, U_b/Dean = the bulk velocity over Dean's.\n\n" + table(rows) + "\n")
 
 
 if __name__ == "__main__":

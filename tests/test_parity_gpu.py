@@ -723,3 +723,48 @@ def test_row_map_multi_block_perturbed_f32(q, nx, ny, nz):
                 _rel_l2(g.lbm_wall()["utau"], o.wall()["utau"]),
                 _rel_l2(g.lbm_populations(), o.f()))
         assert max(errs) < 1e-5, errs
+
+
+# ------------------------------------------------------------- plate, 50 000 steps --
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+_PLATE = dict(nx=2048, ny=256, U=0.1, plate_start=64, lref=992)
+
+
+def _plate_golden(scheme):
+    path = __import__("os").path.join(GOLDEN, f"plate_2048x256_{scheme}.txt")
+    if not __import__("os").path.exists(path):
+        pytest.skip(f"{path} not written yet (tests/golden/make_plate_reference.py {scheme})")
+    rows = np.atleast_2d(np.loadtxt(path))
+    return {int(r[0]): r[1:] for r in rows}
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("scheme", ["slip_bb", "hrfd"])
+def test_config2_plate_50000_steps(scheme, precision):
+    """The 2048 x 256 flat-plate workload (U = 0.1, Re = 5e6 per L_ref = 992
+    cells, 64-column slip section, CM + SA) over 50 000 steps (~2.4
+    flow-throughs), against the FP64 oracle's friction velocity stored at
+    1000, 5000, 20 000 and 50 000 steps (tests/golden, written by
+    make_plate_reference.py): relative L2 of Cf(x) = 2 (u_tau / U)^2 and the
+    integrated error of the plate's second half (trapezoid)."""
+    _torch_gpu()
+    P = _PLATE
+    gold = _plate_golden(scheme)
+    gp = L.lbm_params_default(precision=L.PRECISION[precision], flow=L.LBM_FLOW_PLATE,
+                              scheme=L.SCHEME[scheme], collision=L.LBM_COLL_CM,
+                              nu=P["U"] * P["lref"] / 5e6, u_inlet=P["U"], u_ref=P["U"],
+                              plate_start=P["plate_start"], reduce_every=0)
+    g = L.Lattice(9, P["nx"], P["ny"], 1, gp)
+    g.lbm_set_velocity(inputs.channel_velocity(0, 2, 1, P["ny"], P["nx"], P["U"], 0.0))
+    done = 0
+    tol = {"f64": 1e-9, "f32": 1e-4}[precision]
+    for step in sorted(gold):
+        g.lbm_step(step - done)
+        done = step
+        cf_g = g.lbm_wall()["cf"]  # 2 (u_tau / u_ref)^2 with u_ref = U
+        cf_o = 2.0 * (gold[step] / P["U"]) ** 2
+        err = float(np.linalg.norm(cf_g - cf_o) / np.linalg.norm(cf_o))
+        half = cf_o.size // 2
+        eps = float(np.trapezoid(np.abs(cf_g - cf_o)[half:]) / np.trapezoid(cf_o[half:]))
+        _report(f"plate 2048x256 {precision} {scheme} steps={step}", {"cf_rel_l2": err, "cf_integrated": eps})
+        assert err < tol and eps < tol, (step, err, eps)

@@ -312,3 +312,31 @@ def test_u_tau_criterion_batched_and_sequential():
         assert (b["status"], b["steps"], b["converged_by"]) == (q["status"], q["steps"], q["converged_by"]), r
         if b["status"] == L.LBM_SLOT_CONVERGED:
             assert b["steps"] % 100 == 0 and 0 <= b["d_u_tau_rel"] < 1e-4
+
+
+@pytest.mark.parametrize("wall", ["slip_bb", "hrfd_0.28", "cai_degrigny", "bouzidi_0.75"])
+def test_replication_cases_match_oracle(wall):
+    """Channel cases of the Sec. 4.1 study harness (Table 3 grid, N = 5 and
+    20 at Re_tau 4200, FP64, CM + SA, Dean start), run through the serving
+    pool for 300 steps, against the oracle element-wise (u and u_tau)."""
+    _gpu()
+    from paper_2506_03905_amd import replicate as R
+    if wall == "bouzidi_0.75":
+        cases = [c for c in R.cases(["wall"]) if c["q"] == 0.75]
+    else:
+        cases = [c for c in R.cases(["grid"]) if c["wall"] == wall and c["n"] in (5, 20)]
+    assert cases
+    rows = R.run(cases, tol=0.0, max_steps=300, chunk=150, keep_fields=True)
+    for c, row in zip(cases, rows):
+        ny, h, u_b, u_tau, p = R.lattice_of(c)
+        assert row["steps"] == 300
+        op = O.params(q=9, nx=4, ny=ny, nz=1, scheme=p.scheme, law=p.law, sa_on=p.sa_on, nu=p.nu,
+                      force=tuple(p.force), beta=p.beta, collision=p.collision,
+                      bb_interp=p.bb_interp, wall_dist=p.wall_dist)
+        u0 = np.zeros((2, 1, ny, 4))
+        u0[0] = u_b
+        o = O.Oracle(op, u0)
+        o.step(300)
+        assert np.abs(row["u"] - o.u()).max() / np.abs(o.u()).max() < 1e-10, c
+        ut = o.wall()["utau"]
+        assert np.abs(row["utau"] - ut).max() / ut.max() < 1e-10, c
