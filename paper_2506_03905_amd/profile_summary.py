@@ -11,6 +11,14 @@
       counter reads for a plain device copy of N bytes (it reads and writes N
       bytes), next to the kernel's algorithmic bytes B per launch.
 
+  python -m paper_2506_03905_amd.profile_summary valu --kernel k_step --pmc DIR \
+      --stats KERNEL_STATS_CSV --cells N --cmd "..." > out.md
+      VALU instructions per cell update of each matching kernel from one
+      ``--pmc SQ_INSTS_VALU SQ_WAVES`` run (one wave of 64 lanes updates 64
+      cells), and the share of the kernel's duration (from a kernel-trace run
+      of the same workload) the VALU issue alone needs on MI355X: 256 CUs x 4
+      SIMDs, one wave64 VALU instruction per SIMD every 4 cycles, 2.4 GHz.
+
 The traffic summary ends with a JSON block (fields ``fetch_bytes``,
 ``write_bytes``, ``traffic_bytes``, ``source_sha256``) that ``bench.py``
 reads; ``source_sha256`` is the hash of the kernel sources' code (comments and
@@ -25,7 +33,9 @@ import glob
 import hashlib
 import json
 import os
+import shutil
 import statistics
+import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -65,7 +75,17 @@ def source_sha256() -> str:
     return h.hexdigest()
 
 
+def _demangle(name: str) -> str:
+    if not name.startswith("_Z") or not shutil.which("c++filt"):
+        return name
+    # binutils' c++filt predates the _Float16 mangling DF16_: spell it as half
+    out = subprocess.run(["c++filt", name.replace("DF16_", "Dh")], capture_output=True,
+                         text=True).stdout.strip()
+    return out.replace("half", "_Float16") if out and not out.startswith("_Z") else name
+
+
 def _short(name: str) -> str:
+    name = _demangle(name)
     name = name.replace("(anonymous namespace)::", "").replace("void ", "")
     cut = name.find("(lbmd::KP")
     return name[:cut] if cut > 0 else name[:90]
@@ -124,6 +144,40 @@ def traffic(a) -> str:
     return "\n".join(out) + "\n"
 
 
+def _rows(dirpath: str) -> list:
+    files = glob.glob(os.path.join(dirpath, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {dirpath}")
+    return [r for f in files for r in csv.DictReader(open(f))]
+
+
+def valu(a) -> str:
+    per = {}
+    for r in _rows(a.pmc):
+        if a.kernel not in r["Kernel_Name"]:
+            continue
+        per.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    dur = {}
+    for r in csv.DictReader(open(a.stats)):
+        dur[r["Name"]] = float(r["AverageNs"]) * 1e-9
+    out = ["# VALU instructions per cell update", "", "Commands:", "", "```", a.cmd, "```", "",
+           f"Lattice of {a.cells} cells; one wave of 64 lanes per 64 cells, so VALU instructions "
+           "per wave = per cell update.  Issue time = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x "
+           "2.4 GHz) (one wave64 VALU instruction per SIMD every 4 cycles, no packed math).", "",
+           "| kernel | launches | SQ_INSTS_VALU | SQ_WAVES | VALU per cell | kernel time (us) | VALU issue time (us) | share |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for name, c in sorted(per.items()):
+        v = statistics.mean(c["SQ_INSTS_VALU"])
+        w = statistics.mean(c["SQ_WAVES"])
+        t_issue = v * 4 / (1024 * 2.4e9)
+        short = _short(name)
+        t = dur.get(name)
+        share = f"{t_issue / t:.0%}" if t else "n/a"
+        out.append(f"| `{short}` | {len(c['SQ_INSTS_VALU'])} | {v:.4e} | {w:.0f} | {v / w:.0f} | "
+                   f"{t * 1e6 if t else float('nan'):.1f} | {t_issue * 1e6:.1f} | {share} |")
+    return "\n".join(out) + "\n"
+
+
 def read_traffic(path: str):
     """The JSON block of a traffic summary, or None if it is missing or was
     taken with other kernel sources."""
@@ -155,8 +209,15 @@ def main(argv=None):
     t.add_argument("--copy-kernel", default="copyBuffer")
     t.add_argument("--algorithmic-bytes", type=float, required=True)
     t.add_argument("--cmd", required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("--kernel", required=True)
+    v.add_argument("--pmc", required=True)
+    v.add_argument("--stats", required=True)
+    v.add_argument("--cells", type=int, required=True)
+    v.add_argument("--cmd", required=True)
     a = ap.parse_args(argv)
-    sys.stdout.write(stats(a.csv, a.cmd) if a.mode == "stats" else traffic(a))
+    sys.stdout.write({"stats": lambda: stats(a.csv, a.cmd), "traffic": lambda: traffic(a),
+                      "valu": lambda: valu(a)}[a.mode]())
 
 
 if __name__ == "__main__":
