@@ -268,9 +268,11 @@ int lbm_moments_noalloc(lbm_t *h, void *rho, void *u, void *nu_t, int dtype, int
 /* Copies the SA working variable nu_tilde (ncell, double). */
 int lbm_nu_tilde(lbm_t *h, double *nt, int on_device);
 
-/* Post-collision populations of the last step, f_i (not deviations), in the
- * canonical order, [i*ncell + cell], double; directions that left the domain
- * through an open boundary are reported as NaN.  Synchronous, host only. */
+/* Post-collision populations of the last step, f*_i(x) of eq. 1 before
+ * streaming (not deviations), in the canonical order, [i*ncell + cell],
+ * double.  Every direction of every cell is reported, including those that
+ * stream out through an open boundary at the next step (their post-collision
+ * value, like the rest).  Synchronous, host only. */
 int lbm_populations(lbm_t *h, double *f_host);
 
 /* Per wall cell (in the wall-cell order above), from the wall function of

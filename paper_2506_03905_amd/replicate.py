@@ -77,14 +77,16 @@ def lattice_of(case: dict):
 
 
 def run(case_list: list, tol: float = 1e-9, max_steps: int = 600000, chunk: int = 2000,
-        log=None, keep_fields: bool = False) -> list:
-    """Runs every case to convergence (residual below tol) or max_steps in one
-    pool; keep_fields adds each case's final velocity field and u_tau."""
+        log=None, keep_fields: bool = False, tol_utau: float = 0.0) -> list:
+    """Runs every case to convergence (residual below tol, or, with tol_utau >
+    0, the relative change of the mean u_tau between reductions below
+    tol_utau, the criterion of Sec. 4.1.1) or max_steps in one pool;
+    keep_fields adds each case's final velocity field and u_tau."""
     pool = L.Pool(1 << 30, max_slots=max(len(case_list), 1))
     slots = []
     for c in case_list:
         ny, h, u_b, u_tau, p = lattice_of(c)
-        slots.append((pool.lbm_pool_admit(L.LBM_D2Q9, 4, ny, 1, p, None, tol, max_steps),
+        slots.append((pool.lbm_pool_admit(L.LBM_D2Q9, 4, ny, 1, p, None, tol, max_steps, tol_utau=tol_utau),
                       ny, h, u_b, u_tau))
     t0 = time.perf_counter()
     while True:
@@ -104,6 +106,7 @@ def run(case_list: list, tol: float = 1e-9, max_steps: int = 600000, chunk: int 
         extra = {"u": u, "utau": v.lbm_wall()["utau"]} if keep_fields else {}
         rows.append({**c, **extra, "ny": ny, "steps": s["steps"],
                      "status": {2: "converged", 3: "capped", 4: "diverged"}.get(s["status"], "?"),
+                     "converged_by": {1: "residual", 2: "u_tau"}.get(s.get("converged_by", 0), ""),
                      "residual": s["residual"], "u_tau/target": ut / u_tau,
                      "U_b/dean": ub / u_b, "cf_b/dean": (ut / ub) ** 2 / (u_tau / u_b) ** 2,
                      "y_b_plus": c["q"] * c["re_tau"] / h})
@@ -112,11 +115,13 @@ def run(case_list: list, tol: float = 1e-9, max_steps: int = 600000, chunk: int 
 
 
 def table(rows: list) -> str:
-    out = ["| study | Re_tau | N | wall | q | steps | status | u_tau/target | U_b/Dean |",
-           "|---|---:|---:|---|---:|---:|---|---:|---:|"]
+    out = ["| study | Re_tau | N | wall | q | steps | status | residual | u_tau/target | U_b/Dean |",
+           "|---|---:|---:|---|---:|---:|---|---:|---:|---:|"]
     for r in rows:
+        st = r["status"] + (f" ({r['converged_by']})" if r.get("converged_by") else "")
         out.append(f"| {r['study']} | {r['re_tau']:.0f} | {r['n']} | {r['wall']} | {r['q']:g} | "
-                   f"{r['steps']} | {r['status']} | {r['u_tau/target']:.4f} | {r['U_b/dean']:.4f} |")
+                   f"{r['steps']} | {st} | {r['residual']:.1e} | {r['u_tau/target']:.4f} | "
+                   f"{r['U_b/dean']:.4f} |")
     return "\n".join(out)
 
 
@@ -125,11 +130,14 @@ def main(argv=None):
     ap.add_argument("--studies", default="grid,reynolds,beta,wall")
     ap.add_argument("--max-steps", type=int, default=600000)
     ap.add_argument("--tol", type=float, default=1e-9)
+    ap.add_argument("--tol-utau", type=float, default=0.0,
+                    help="also retire a case once its mean u_tau changes by less than this "
+                         "(relative) between reductions (Sec. 4.1.1 uses 1e-4)")
     ap.add_argument("--json", action="store_true")
     ap.add_argument("--out", default=None, help="also write the table (markdown) to this file")
     a = ap.parse_args(argv)
     t0 = time.perf_counter()
-    rows = run(cases(a.studies.split(",")), tol=a.tol, max_steps=a.max_steps,
+    rows = run(cases(a.studies.split(",")), tol=a.tol, max_steps=a.max_steps, tol_utau=a.tol_utau,
                log=lambda m: print("# " + m, file=sys.stderr, flush=True))
     text = json.dumps(rows) if a.json else table(rows)
     print(text, flush=True)
@@ -137,7 +145,7 @@ def main(argv=None):
         with open(a.out, "w") as fh:
             fh.write("# Channel studies of Sec. 4.1 (written by paper_2506_03905_amd.replicate)\n\n"
                      f"Command: `python -m paper_2506_03905_amd.replicate --studies {a.studies} "
-                     f"--max-steps {a.max_steps} --tol {a.tol:g} --out {a.out}`; "
+                     f"--max-steps {a.max_steps} --tol {a.tol:g} --tol-utau {a.tol_utau:g} --out {a.out}`; "
                      f"{len(rows)} channels in one serving pool, {time.perf_counter() - t0:.1f} s on one "
                      "MI355X.  D2Q9 4 x 2N, FP64, central-moment collision + SA, Dean start; "
                      "u_tau/target = the wall function's mean friction velocity over the one the "
