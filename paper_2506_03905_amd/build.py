@@ -15,6 +15,10 @@ def hipcc_cmd(out: str) -> list:
         "hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
         # packed FP32 instructions are disabled on this target family by choice
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # the step kernels read their by-value parameter block in several
+        # inlined copies of the cell update; above LLVM's default of 300 uses
+        # the block is copied to scratch memory instead of being read in place
+        "-mllvm", "-instcombine-max-copied-from-constant-users=4096",
         "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
         "-I", os.path.join(ROOT, "include"), *SRC, "-o", out,
     ]

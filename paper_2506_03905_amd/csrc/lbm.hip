@@ -102,7 +102,11 @@ template <int Q> __device__ __forceinline__ int64_t pidx(int nx, int q, int x, i
     return (row * Q + q) * (int64_t)nx + x;
 }
 
-template <int Q, bool PLATE> __device__ __forceinline__ Cell make_cell(const KP &P, int x, int y, int z, bool active)
+// INT: the cell's row is known to hold neither a wall cell nor a symmetry
+// plane (an interior row of the channel's row mapping), so every boundary
+// test below folds away at compile time.
+template <int Q, bool PLATE, bool INT = false>
+__device__ __forceinline__ Cell make_cell(const KP &P, int x, int y, int z, bool active)
 {
     Cell C;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
@@ -117,9 +121,9 @@ template <int Q, bool PLATE> __device__ __forceinline__ Cell make_cell(const KP 
     C.oxp = (x == nx - 1) ? (PLATE ? 0 : -(int64_t)(nx - 1)) : 1;
     C.ozm = (z == 0) ? (int64_t)(nz - 1) * C.sz : -C.sz;
     C.ozp = (z == nz - 1) ? -(int64_t)(nz - 1) * C.sz : C.sz;
-    C.bottom = (y == 0);
-    C.top = (y == ny - 1);
-    C.wi = active ? wall_index(P, x, y, z) : -1;
+    C.bottom = !INT && y == 0;
+    C.top = !INT && y == ny - 1;
+    C.wi = (active && !INT) ? wall_index(P, x, y, z) : -1;
     return C;
 }
 
@@ -308,7 +312,7 @@ __device__ __forceinline__ void sa_cell(const KP &P, const Cell &C, int rd, T nt
     }
     // y neighbours (plate symmetry planes: mirror image, same tangential velocity)
     {
-        const int64_t cm = (y == 0) ? cell : cell - sy, cp = (y == ny - 1) ? cell : cell + sy;
+        const int64_t cm = C.bottom ? cell : cell - sy, cp = C.top ? cell : cell + sy;
         ntm[1] = nt_rd[cm];
         ntp[1] = nt_rd[cp];
         g[0][1] = (u_rd[cp] - u_rd[cm]) * (T)0.5;
@@ -501,6 +505,9 @@ __device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S 
     Cell Cs = C;
     if (ODD) asm volatile("" : "+v"(Cs.pb), "+v"(Cs.oxm), "+v"(Cs.oxp), "+v"(Cs.ozm), "+v"(Cs.ozp));
     const int64_t pbs = Cs.pb;
+    // staged pushes: the block's columns [x - tid, x - tid + xs_lim) lie in the
+    // row, so a push to block column t stays in the row iff 0 <= t < xs_lim
+    const int xs_lim = XS ? min(BLK, nx - (x - (int)threadIdx.x)) : 0;
     if (P.shifted) sfor<Q>([&](auto ic) { f[decltype(ic)::value] -= K.soff[decltype(ic)::value]; });
     sfor<Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
@@ -520,8 +527,8 @@ __device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S 
                 idx = !ycross ? pbs + i * nx + poff<Q>(Cs, ccxi, ccyi, cczi)
                               : (wall ? pbs + io * nx : pbs + im * nx + poff<Q>(Cs, ccxi, 0, cczi));
             if constexpr (XS && ccxi != 0) {
-                const int xd = x + ccxi, t = (int)threadIdx.x + ccxi;
-                if (!ycross && xd >= 0 && xd < nx && t >= 0 && t < BLK) {
+                const int t = (int)threadIdx.x + ccxi;
+                if (!ycross && (unsigned)t < (unsigned)xs_lim) {
                     lds[xslot<Q>(i) * BLK + t] = SS::st(fp);
                     return;
                 }
@@ -575,12 +582,12 @@ __device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S 
 // IBB: interpolated bounce-back links may be present (else the halfway rule
 // is compiled in alone, keeping the common kernels lean).
 template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false, bool IBB = false,
-          bool RED = false>
+          bool RED = false, bool INT = false>
 __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, int z, bool active, RedAcc *ra = nullptr)
 {
     const int nx = P.nx;
     const int tid = threadIdx.x;
-    const Cell C = make_cell<Q, PLATE>(P, x, y, z, active);
+    const Cell C = make_cell<Q, PLATE, INT>(P, x, y, z, active);
     if constexpr (XS) {
         // a block covers columns [x - tid, x - tid + BLK) of one row
         __shared__ S lds[nxdirs<Q>() * BLK];
@@ -593,13 +600,14 @@ __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, i
         }
         __syncthreads();
         S *__restrict__ A = (S *)P.pops;
+        const int xs_lim = min(BLK, nx - (x - tid));  // the block's columns in the row
         sfor<Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int ccx = cx<Q>(i), ccy = cy<Q>(i), ccz = cz<Q>(i);
             if constexpr (ccx != 0) {
                 const bool ycross = (ccy < 0 && C.bottom) || (ccy > 0 && C.top);
                 const int src = tid - ccx;  // thread that staged column x
-                if (active && !ycross && src >= 0 && src < BLK && x - ccx >= 0 && x - ccx < nx)
+                if (active && !ycross && (unsigned)src < (unsigned)xs_lim)
                     st_pop(&A[C.pb + i * nx + poff<Q>(C, 0, ccy, ccz)], lds[xslot<Q>(i) * BLK + tid]);
             }
         });
@@ -647,10 +655,29 @@ __device__ __forceinline__ void plate_block(int nx, int64_t b, int tid, int &x, 
 // steps that end a reduction interval): each block also writes its FP64
 // partial sums of slots 0-6 to P.partials[blockIdx.x].
 // ---------------------------------------------------------------------------
+// One cell update of k_step; XS: the staged odd step of the row mapping;
+// INT: the block's row is interior (known per block).
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool IBB, bool RED, bool XS,
+          bool INT>
+__device__ __forceinline__ void step_cell(const KP &P, int rd, int x, int y, int z, bool active)
+{
+    if constexpr (RED) {
+        RedAcc ra = {};
+        cell_update<Q, S, T, ODD, PLATE, HRFD, CMC, false, IBB, true, INT>(P, rd, x, y, z, active, &ra);
+        __shared__ double sh[7][BLK];
+        block_sum<BLK>(sh, ra.v, 7);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 7; ++k) P.partials[(int64_t)blockIdx.x * NRED + k] = sh[k][0];
+    } else {
+        cell_update<Q, S, T, ODD, PLATE, HRFD, CMC, XS, IBB, false, INT>(P, rd, x, y, z, active);
+    }
+}
+
 template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool IBB, bool RED = false>
 __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
 {
     static_assert(!RED || (!ODD && !PLATE), "the fused reduction is built for even channel steps");
+    constexpr bool XS = ODD && !PLATE && LBM_XSTAGE;
     const int nx = P.nx, ny = P.ny;
     const int64_t N = P.ncell;
     const int tid = threadIdx.x;
@@ -660,6 +687,8 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         // XCD k (hardware block b -> XCD b % 8) owns the rows y in
         // [k ny/8, (k+1) ny/8) for every z, walked z-major: the z+-1 and y+-1
         // neighbours of the SA stencil are then a few rows apart in one L2.
+        // A block covers BLK consecutive columns of one row, so whether the
+        // row is a wall row is known per block.
         const uint32_t b = blockIdx.x, xcd = b & 7u, l = b >> 3;
         const uint32_t nseg = (uint32_t)((nx + BLK - 1) / BLK), rows = (uint32_t)ny >> 3;
         const uint32_t seg = l % nseg, r = l / nseg;
@@ -667,11 +696,13 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         z = (int)(r / rows);
         x = (int)(seg * BLK) + tid;
         active = x < nx;
-        if constexpr (ODD && !PLATE && LBM_XSTAGE) {
-            cell_update<Q, S, T, ODD, PLATE, HRFD, CMC, true, IBB>(P, rd, x, y, z, active);
-            return;
-        }
-    } else if (!PLATE) {
+        if (y != 0 && y != ny - 1)
+            step_cell<Q, S, T, ODD, PLATE, HRFD, CMC, IBB, RED, XS, true>(P, rd, x, y, z, active);
+        else
+            step_cell<Q, S, T, ODD, PLATE, HRFD, CMC, IBB, RED, XS, false>(P, rd, x, y, z, active);
+        return;
+    }
+    if (!PLATE) {
         const int64_t cell = xcd_block(blockIdx.x, gridDim.x) * BLK + tid;
         active = cell < N;
         const int64_t r = cell / nx;
@@ -684,16 +715,8 @@ __global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
         z = 0;
         active = x >= 0;
     }
-    if constexpr (RED) {
-        RedAcc ra = {};
-        cell_update<Q, S, T, ODD, PLATE, HRFD, CMC, false, IBB, true>(P, rd, x, y, z, active, &ra);
-        __shared__ double sh[7][BLK];
-        block_sum<BLK>(sh, ra.v, 7);
-        if (tid == 0)
-            for (int k = 0; k < 7; ++k) P.partials[(int64_t)blockIdx.x * NRED + k] = sh[k][0];
-    } else {
-        cell_update<Q, S, T, ODD, PLATE, HRFD, CMC, false, IBB>(P, rd, x, y, z, active);
-    }
+    // (the staged store needs the row mapping)
+    step_cell<Q, S, T, ODD, PLATE, HRFD, CMC, IBB, RED, false, false>(P, rd, x, y, z, active);
 }
 
 // ---------------------------------------------------------------------------
