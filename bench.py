@@ -261,7 +261,7 @@ def main():
     ap.add_argument("--ny", type=int, default=None)
     ap.add_argument("--nz", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--collision", default="bgk", choices=["bgk", "cm"])
     ap.add_argument("--amp", type=float, default=0.0)
     ap.add_argument("--store-shift", type=float, default=0.0,

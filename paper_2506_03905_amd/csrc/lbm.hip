@@ -673,8 +673,12 @@ __device__ __forceinline__ void step_cell(const KP &P, int rd, int x, int y, int
     }
 }
 
+// With 16-bit storage the step is limited by instruction issue more than by
+// HBM, and five waves per SIMD (at most 96 VGPRs) beat four; FP32 and FP64
+// keep the compiler's register allocation (five waves cost FP32 4 %).
 template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool IBB, bool RED = false>
-__global__ void __launch_bounds__(BLK) k_step(KP P, int rd)
+__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 2 ? 5 : 1, 8)))
+k_step(KP P, int rd)
 {
     static_assert(!RED || (!ODD && !PLATE), "the fused reduction is built for even channel steps");
     constexpr bool XS = ODD && !PLATE && LBM_XSTAGE;
