@@ -165,7 +165,9 @@ template <int Q> __host__ __device__ constexpr int xslot(int i)
 // the wall links (eq. 31) and symmetry planes resolved; the open-boundary
 // unknowns of the plate are left at 0 for plate_edges.
 // ---------------------------------------------------------------------------
-template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool IBB = false>
+// FOLD: the storage shift is left on the values (the collision works on the
+// stored values, see finish).
+template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool IBB = false, bool FOLD = false>
 __device__ __forceinline__ void gather(const KP &P, const Cell &C, T *f)
 {
     using SS = Stor<S>;
@@ -201,7 +203,7 @@ __device__ __forceinline__ void gather(const KP &P, const Cell &C, T *f)
         f[i] = SS::ld(ld_pop(&A[idx]));
     });
     // storage shift of the population the slot held (uniform branch)
-    if (P.shifted)
+    if (!FOLD && P.shifted)
         sfor<Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int ccx = cx<Q>(i), ccy = cy<Q>(i);
@@ -354,13 +356,72 @@ struct RedAcc {
     double v[7];
 };
 
+// BGK collision with Guo forcing of one cell (see finish).  SH: f holds the
+// stored values f - soff of the storage shift, and the relaxation targets
+// f_eq - soff, so that f* - soff is what is left in f.
+template <int Q, typename T, bool SH>
+__device__ __forceinline__ void bgk_collide(const CellK<T> &K, T *f, T drho, T rho, T ux, T uy, T uz, T jx, T jy,
+                                            T jz, T omega)
+{
+    constexpr int D = Lat<Q>::D;
+    const T Fx = K.fx, Fy = K.fy, Fz = K.fz;
+    // BGK with Guo forcing, f* = f - omega (f - f_eq) + S with
+    //   f_eq_i = w_i (drho + rho (3 cu + 9/2 cu^2 - 3/2 u.u))      (deviation form)
+    //   S_i    = (1 - omega/2) w_i (3 (c_i.F - u.F) + 9 cu (c_i.F)),  cu = c_i.u
+    // taken per pair (i, opp(i)): the parts even in c_i are shared by the
+    // pair, the odd parts change sign.  The relaxation acts on f - f_eq:
+    // written as (1 - omega) f + omega f_eq, the rounding of 1 - omega
+    // (omega near 2) leaves (1 - omega) + omega != 1 in the momentum sum, a
+    // bias of ulp(1) * rho u per step that the FP32 path accumulated to
+    // 1e-4 of u within 1000 steps (the body force is ~1e-8 per step).
+    const T uu = ux * ux + uy * uy + uz * uz;
+    const T fpref = (T)1 - (T)0.5 * omega;
+    const T uF = ux * Fx + uy * Fy + uz * Fz;
+    // r = rho u - (j + F/2): the first moment the equilibrium carries minus
+    // the one eq. 5 gives it, exact to the rounding of a small number.  The
+    // half-force shift is a few ulp of j in FP32, so the rounding of u is
+    // the same at every step and would bias the momentum input by up to a
+    // tenth of the body force per step; the source removes omega r.
+    const T rx = fma(rho, ux, -jx) - (T)0.5 * Fx, ry = fma(rho, uy, -jy) - (T)0.5 * Fy;
+    const T rz = D == 3 ? fma(rho, uz, -jz) - (T)0.5 * Fz : (T)0;
+    // odd part of the source per unit weight: 3 c_i . G, G = (1 - omega/2) F - omega r
+    const T Gx = (T)3 * (fpref * Fx - omega * rx), Gy = (T)3 * (fpref * Fy - omega * ry);
+    const T Gz = (T)3 * (fpref * Fz - omega * rz);
+    // per unit weight: the c-independent parts of f_eq and of S
+    const T e0 = drho - (T)1.5 * rho * uu;
+    const T s0 = (T)-3 * fpref * uF;
+    const T r45 = (T)4.5 * rho, r3 = (T)3 * rho;
+    const T f9 = (T)9 * fpref;
+    {
+        const T w0 = (T)wgt<Q>(0);
+        const T e = SH ? w0 * e0 - K.sfe[0] : w0 * e0;
+        f[0] = (f[0] - omega * (f[0] - e)) + w0 * s0;
+    }
+    sfor<(Q - 1) / 2>([&](auto kc) {
+        constexpr int i = 2 * decltype(kc)::value + 1, io = opp<Q>(i);
+        static_assert(io == i + 1, "pairs (2k+1, 2k+2)");
+        const T w = (T)wgt<Q>(i);
+        const T cu = (T)cx<Q>(i) * ux + (T)cy<Q>(i) * uy + (T)cz<Q>(i) * uz;
+        T E = w * (e0 + r45 * (cu * cu)), O = (w * r3) * cu;   // f_eq = E +- O
+        if constexpr (SH) {
+            E -= K.sfe[decltype(kc)::value + 1];
+            O -= K.sfo[decltype(kc)::value + 1];
+        }
+        const T Se = w * s0 + (f9 * K.cf[i]) * cu;                     // S = Se +- So
+        const T So = w * ((T)cx<Q>(i) * Gx + (T)cy<Q>(i) * Gy + (T)cz<Q>(i) * Gz);
+        const T ti = f[i] - (E + O), tio = f[io] - (E - O);
+        f[i] = (f[i] - omega * ti) + (Se + So);
+        f[io] = (f[io] - omega * tio) + (Se - So);
+    });
+}
+
 // ---------------------------------------------------------------------------
 // finish: HRFD reconstruction (wall cells), moments, collision, AA store,
 // velocity, wall density and the Spalart-Allmaras update of one cell.
 // rd: ping-pong index of u^{n-1} / nu_tilde^n; results go to rd ^ 1.
 // ---------------------------------------------------------------------------
 template <int Q, typename S, typename T, bool ODD, bool PLATE, bool HRFD, bool CMC, bool XS = false, bool IBB = false,
-          bool RED = false>
+          bool RED = false, bool INT = false>
 __device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S *lds = nullptr, RedAcc *ra = nullptr)
 {
     constexpr int D = Lat<Q>::D;
@@ -436,6 +497,18 @@ __device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S 
         if constexpr (cz<Q>(i) > 0) jz += f[i];
         if constexpr (cz<Q>(i) < 0) jz -= f[i];
     });
+    // FOLD (interior rows, BGK, 16-bit storage): f holds the stored values
+    // f - soff; the moments add the offsets' sums, and the collision relaxes
+    // the stored values towards f_eq - soff, which leaves f* - soff to be
+    // stored.  It saves two additions per population where the instruction
+    // issue bounds the step; FP32 and FP64 keep the plain order of operations.
+    constexpr bool FOLD = INT && !CMC && sizeof(S) == 2;
+    if (FOLD && P.shifted) {
+        drho += K.ssum;
+        jx += K.sj[0];
+        jy += K.sj[1];
+        jz += K.sj[2];
+    }
     const T rho = K.rho0 + drho;
     const T Fx = K.fx, Fy = K.fy, Fz = K.fz;
     const T inv = Num<T>::rcp(rho);
@@ -449,49 +522,7 @@ __device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S 
         const T uvec[3] = {ux, uy, uz}, Fv[3] = {Fx, Fy, Fz};
         cm_collide<Q, T>(f, drho, rho, uvec, Fv, omega);
     } else {
-        // BGK with Guo forcing, f* = f - omega (f - f_eq) + S with
-        //   f_eq_i = w_i (drho + rho (3 cu + 9/2 cu^2 - 3/2 u.u))      (deviation form)
-        //   S_i    = (1 - omega/2) w_i (3 (c_i.F - u.F) + 9 cu (c_i.F)),  cu = c_i.u
-        // taken per pair (i, opp(i)): the parts even in c_i are shared by the
-        // pair, the odd parts change sign.  The relaxation acts on f - f_eq:
-        // written as (1 - omega) f + omega f_eq, the rounding of 1 - omega
-        // (omega near 2) leaves (1 - omega) + omega != 1 in the momentum sum, a
-        // bias of ulp(1) * rho u per step that the FP32 path accumulated to
-        // 1e-4 of u within 1000 steps (the body force is ~1e-8 per step).
-        const T uu = ux * ux + uy * uy + uz * uz;
-        const T fpref = (T)1 - (T)0.5 * omega;
-        const T uF = ux * Fx + uy * Fy + uz * Fz;
-        // r = rho u - (j + F/2): the first moment the equilibrium carries minus
-        // the one eq. 5 gives it, exact to the rounding of a small number.  The
-        // half-force shift is a few ulp of j in FP32, so the rounding of u is
-        // the same at every step and would bias the momentum input by up to a
-        // tenth of the body force per step; the source removes omega r.
-        const T rx = fma(rho, ux, -jx) - (T)0.5 * Fx, ry = fma(rho, uy, -jy) - (T)0.5 * Fy;
-        const T rz = D == 3 ? fma(rho, uz, -jz) - (T)0.5 * Fz : (T)0;
-        // odd part of the source per unit weight: 3 c_i . G, G = (1 - omega/2) F - omega r
-        const T Gx = (T)3 * (fpref * Fx - omega * rx), Gy = (T)3 * (fpref * Fy - omega * ry);
-        const T Gz = (T)3 * (fpref * Fz - omega * rz);
-        // per unit weight: the c-independent parts of f_eq and of S
-        const T e0 = drho - (T)1.5 * rho * uu;
-        const T s0 = (T)-3 * fpref * uF;
-        const T r45 = (T)4.5 * rho, r3 = (T)3 * rho;
-        const T f9 = (T)9 * fpref;
-        {
-            const T w0 = (T)wgt<Q>(0);
-            f[0] = (f[0] - omega * (f[0] - w0 * e0)) + w0 * s0;
-        }
-        sfor<(Q - 1) / 2>([&](auto kc) {
-            constexpr int i = 2 * decltype(kc)::value + 1, io = opp<Q>(i);
-            static_assert(io == i + 1, "pairs (2k+1, 2k+2)");
-            const T w = (T)wgt<Q>(i);
-            const T cu = (T)cx<Q>(i) * ux + (T)cy<Q>(i) * uy + (T)cz<Q>(i) * uz;
-            const T E = w * (e0 + r45 * (cu * cu)), O = (w * r3) * cu;   // f_eq = E +- O
-            const T Se = w * s0 + (f9 * K.cf[i]) * cu;                     // S = Se +- So
-            const T So = w * ((T)cx<Q>(i) * Gx + (T)cy<Q>(i) * Gy + (T)cz<Q>(i) * Gz);
-            const T ti = f[i] - (E + O), tio = f[io] - (E - O);
-            f[i] = (f[i] - omega * ti) + (Se + So);
-            f[io] = (f[io] - omega * tio) + (Se - So);
-        });
+        bgk_collide<Q, T, FOLD>(K, f, drho, rho, ux, uy, uz, jx, jy, jz, omega);
     }
     // post-collision populations of a wall cell for its interpolated links
     if (IBB && P.bb_interp != IBB_HALFWAY && wi >= 0)
@@ -508,7 +539,7 @@ __device__ __forceinline__ T finish(const KP &P, const Cell &C, int rd, T *f, S 
     // staged pushes: the block's columns [x - tid, x - tid + xs_lim) lie in the
     // row, so a push to block column t stays in the row iff 0 <= t < xs_lim
     const int xs_lim = XS ? min(BLK, nx - (x - (int)threadIdx.x)) : 0;
-    if (P.shifted) sfor<Q>([&](auto ic) { f[decltype(ic)::value] -= K.soff[decltype(ic)::value]; });
+    if (!FOLD && P.shifted) sfor<Q>([&](auto ic) { f[decltype(ic)::value] -= K.soff[decltype(ic)::value]; });
     sfor<Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int ccxi = cx<Q>(i), ccyi = cy<Q>(i), cczi = cz<Q>(i);
@@ -594,9 +625,9 @@ __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, i
         T f[Q];
         T nt0 = 0;
         if (active) {
-            gather<Q, S, T, ODD, PLATE, HRFD, IBB>(P, C, f);
+            gather<Q, S, T, ODD, PLATE, HRFD, IBB, INT && !CMC && sizeof(S) == 2>(P, C, f);
             if constexpr (IBB && !HRFD) ibb_links<Q, T, false>(P, C, f);
-            nt0 = finish<Q, S, T, ODD, PLATE, HRFD, CMC, true, IBB>(P, C, rd, f, lds);
+            nt0 = finish<Q, S, T, ODD, PLATE, HRFD, CMC, true, IBB, false, INT>(P, C, rd, f, lds);
         }
         __syncthreads();
         S *__restrict__ A = (S *)P.pops;
@@ -617,7 +648,7 @@ __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, i
         return;
     }
     T f[Q];
-    if (active) gather<Q, S, T, ODD, PLATE, HRFD, IBB>(P, C, f);
+    if (active) gather<Q, S, T, ODD, PLATE, HRFD, IBB, INT && !CMC && sizeof(S) == 2>(P, C, f);
     if constexpr (IBB && !HRFD)
         if (active && (!PLATE || x != nx - 1)) ibb_links<Q, T, PLATE>(P, C, f);
     if (PLATE) {
@@ -638,7 +669,7 @@ __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, i
         if (active && x == 0) zou_he(P, f);
     }
     if (!active) return;
-    finish<Q, S, T, ODD, PLATE, HRFD, CMC, false, IBB, RED>(P, C, rd, f, nullptr, ra);
+    finish<Q, S, T, ODD, PLATE, HRFD, CMC, false, IBB, RED, INT>(P, C, rd, f, nullptr, ra);
 }
 
 // plate mapping: rows aligned to the right end, nseg blocks per row
@@ -1581,6 +1612,21 @@ template <typename T> void fill_cellk(const KP &k, int Q, CellK<T> &c)
         c.cf[i] = (T)(w * (cv[0] * k.fx + cv[1] * k.fy + cv[2] * k.fz));
         if (k.shift_u != 0.0)
             c.soff[i] = (T)(Q == 9 ? shift_off<9, double>(i, k.rho0, k.shift_u) : shift_off<19, double>(i, k.rho0, k.shift_u));
+    }
+    // the same offsets as the collision on stored values uses them (from the
+    // rounded soff, so that both forms see the same numbers)
+    double ssum = 0, sj[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+        const int *cv = Q == 9 ? Lat<9>::c[i] : Lat<19>::c[i];
+        ssum += (double)c.soff[i];
+        for (int a = 0; a < 3; ++a) sj[a] += cv[a] * (double)c.soff[i];
+    }
+    c.ssum = (T)ssum;
+    for (int a = 0; a < 3; ++a) c.sj[a] = (T)sj[a];
+    c.sfe[0] = c.soff[0];
+    for (int kp = 1; 2 * kp < Q; ++kp) {
+        c.sfe[kp] = (T)(0.5 * ((double)c.soff[2 * kp - 1] + (double)c.soff[2 * kp]));
+        c.sfo[kp] = (T)(0.5 * ((double)c.soff[2 * kp - 1] - (double)c.soff[2 * kp]));
     }
 }
 

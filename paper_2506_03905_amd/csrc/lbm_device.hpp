@@ -145,6 +145,12 @@ template <typename T> struct CellK {
     T inv_sigma, wall_dist;
     T cf[19];    // w_i (c_i . F), the direction's share of the Guo forcing term
     T soff[19];  // storage offset of population i (zero without the storage shift)
+    // the storage offsets split for the collision on stored values: sfe[0] =
+    // soff[0], and for the pair k = (2k-1, 2k) the even and odd parts
+    // sfe[k] = (soff[2k-1] + soff[2k]) / 2, sfo[k] = (soff[2k-1] - soff[2k]) / 2;
+    // ssum = sum of soff, sj = sum of c_i soff (zero without the shift)
+    T sfe[10], sfo[10];
+    T ssum, sj[3];
 };
 
 // ---------------------------------------------------------------------------
