@@ -169,16 +169,18 @@ def serving_bench(args):
     print(f"# serving: {len(reqs)} requests, total footprint {need / 1e9:.2f} GB, "
           f"pool {pool_bytes / 1e9:.2f} GB", file=sys.stderr, flush=True)
     res_b, sum_b = serving.run_batched(reqs, pool_bytes, chunk=args.chunk, tol=args.tol,
-                                       max_steps=args.max_steps, log=log)
+                                       tol_utau=args.tol_utau, max_steps=args.max_steps, log=log)
     torch.cuda.synchronize()
     nseq = len(reqs) if args.seq_requests < 0 else min(args.seq_requests, len(reqs))
     seq = reqs[:nseq]
-    res_s, sum_s = serving.run_sequential(seq, tol=args.tol, max_steps=args.max_steps, log=log)
+    res_s, sum_s = serving.run_sequential(seq, tol=args.tol, tol_utau=args.tol_utau,
+                                          max_steps=args.max_steps, log=log)
     # same requests, same result: step counts and end status must agree, and
     # the mean u_tau at the end (FP32 fields; the two paths differ only in the
     # order of FP64 sums and in FMA contraction)
     agree = all(res_b[r["id"]]["status"] == res_s[r["id"]]["status"] and
-                res_b[r["id"]]["steps"] == res_s[r["id"]]["steps"] for r in seq)
+                res_b[r["id"]]["steps"] == res_s[r["id"]]["steps"] and
+                res_b[r["id"]]["converged_by"] == res_s[r["id"]]["converged_by"] for r in seq)
     dut = [abs(res_b[r["id"]]["mean_u_tau"] - res_s[r["id"]]["mean_u_tau"]) /
            max(abs(res_s[r["id"]]["mean_u_tau"]), 1e-300) for r in seq
            if res_s[r["id"]]["status"] != 4 and res_b[r["id"]]["status"] != 4]
@@ -197,7 +199,8 @@ def serving_bench(args):
         "data": "synthetic",
         "config": {"workload": f"serving: {len(reqs)} Poisson requests at {args.rate:g}/s, 70% "
                                f"2-D channel (4 x Ny) / 30% flat plate (8Ny x Ny), Ny log-uniform "
-                               f"[32, 1024], Re_tau log-uniform [500, 20000], tol {args.tol:g}, "
+                               f"[32, 1024], Re_tau log-uniform [500, 20000], retired on residual < "
+                               f"{args.tol:g} or d(u_tau)/u_tau < {args.tol_utau:g} per 100 steps, "
                                f"step cap {args.max_steps}, D2Q9 FP32 CM + SA",
                    "chunk": args.chunk, "parallelism": "single GPU"},
         "batched": sum_b,
