@@ -725,6 +725,31 @@ def test_row_map_multi_block_perturbed_f32(q, nx, ny, nz):
         assert max(errs) < 1e-5, errs
 
 
+
+@pytest.mark.parametrize("precision,tol", [("f16", 1e-3), ("bf16", 1e-2)])
+@pytest.mark.parametrize("q,nx,ny,nz", [(19, 512, 16, 4), (9, 768, 16, 1)])
+def test_row_map_multi_block_perturbed_16bit(q, nx, ny, nz, precision, tol):
+    """16-bit storage of the deviation from the bulk equilibrium (the layout
+    whose interior rows run the collision on the stored values) on the same
+    perturbed row-mapped lattices, against the FP64 oracle after 1, 2 and 30
+    more steps: u, nu_tilde, u_tau and the populations within the FP16
+    target (BF16: a guard ten times wider)."""
+    lat = units.channel(5000.0, ny // 2)
+    u0 = _channel_u0(q, nx, ny, nz, lat["u_bulk"], amp=1e-3, seed=12)
+    o, g = _pair(q, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"] * 10, 0, 0), precision=precision,
+                 store_shift_u=lat["u_bulk"])
+    for n in (1, 1, 30):
+        o.step(n)
+        g.lbm_step(n)
+        _, ug, _ = g.lbm_moments()
+        errs = (_rel_l2(ug, o.u()), _rel_l2(g.lbm_nu_tilde(), o.nt()),
+                _rel_l2(g.lbm_wall()["utau"], o.wall()["utau"]),
+                _rel_l2(g.lbm_populations(), o.f()))
+        _report(f"{q} {nx}x{ny}x{nz} row-map perturbed {precision} shift=1 steps+={n}",
+                {"u_rel_l2": errs[0], "nt_rel_l2": errs[1], "u_tau_rel_l2": errs[2], "f_rel_l2": errs[3]})
+        assert max(errs) < tol, errs
+
 # ------------------------------------------------------------- plate, 50 000 steps --
 GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
 _PLATE = dict(nx=2048, ny=256, U=0.1, plate_start=64, lref=992)
