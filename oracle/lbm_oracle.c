@@ -13,7 +13,10 @@
  * stated next to the code.  Readings in force:
  *   - collision is BGK (the paper's base model, Sec. 2.1) with the
  *     second-order equilibrium and Guo forcing weighted by (1 - omega/2),
- *     the BGK form of the (I - Lambda/2) R source of eq. 7;
+ *     the BGK form of the (I - Lambda/2) R source of eq. 7, or the
+ *     central-moment operator of eq. 7 itself (orc_collide_cm: T built from
+ *     the definition of the central moments, T f* = k* solved by Gaussian
+ *     elimination);
  *   - the velocity is the half-force-shifted first moment (eq. 5);
  *   - rho_w in eq. 31 is the post-collision density of the boundary cell;
  *   - the u_tau reference node F is the second node off the wall (Sec. 3.1),
@@ -25,6 +28,10 @@
  *     off and r = r_lim when S_tilde <= 0, nu_tilde clipped at 0;
  *   - eq. 35 uses nu_t|B = nu kappa y_B+ and Delta_w = y_B, with the LBM
  *     velocity at B from the previous step.
+ * Pins: every routine is checked against closed forms, invariants or the
+ * paper's tables on the CPU, and a set of planted single-line mistakes must
+ * each fail one of those checks.  The coupled step as a whole has no closed
+ * form; its parity rests on those pieces.
  */
 #include "lbm_oracle.h"
 
