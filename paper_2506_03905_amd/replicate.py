@@ -17,6 +17,12 @@ Studies (only formulas of the paper are needed):
             interpolated bounce-back (Sec. 4.1.2.5)
 
     python -m paper_2506_03905_amd.replicate [--studies grid,beta] [--max-steps N]
+        [--tol R] [--tol-utau T] [--out table.md]
+
+A case retires when the residual falls below --tol or, with --tol-utau > 0,
+when the mean u_tau changes by less than that (relative) between two
+reductions (100 steps apart), the criterion of Sec. 4.1.1; the table says
+which fired.
 """
 from __future__ import annotations
 
