@@ -620,8 +620,13 @@ __device__ __forceinline__ void cell_update(const KP &P, int rd, int x, int y, i
     const int tid = threadIdx.x;
     const Cell C = make_cell<Q, PLATE, INT>(P, x, y, z, active);
     if constexpr (XS) {
-        // a block covers columns [x - tid, x - tid + BLK) of one row
-        __shared__ S lds[nxdirs<Q>() * BLK];
+        // a block covers columns [x - tid, x - tid + BLK) of one row.  The
+        // FP32 D3Q19 odd step runs fastest at four blocks per CU (fewer
+        // neighbour-row streams in flight: 0.8 % faster at 512x256x256 and
+        // 1.5 % at 768x384x384 than at five, while three are slower); its
+        // staging array is sized so that LDS holds the CU at four.
+        constexpr int lds_rows = (Q == 19 && sizeof(S) == 4) ? 2 : 1;
+        __shared__ S lds[nxdirs<Q>() * BLK * lds_rows];
         T f[Q];
         T nt0 = 0;
         if (active) {
