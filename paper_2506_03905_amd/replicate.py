@@ -151,7 +151,7 @@ def main(argv=None):
         with open(a.out, "w") as fh:
             fh.write("# Channel studies of Sec. 4.1 (written by paper_2506_03905_amd.replicate)\n\n"
                      f"Command: `python -m paper_2506_03905_amd.replicate --studies {a.studies} "
-                     f"--max-steps {a.max_steps} --tol {a.tol:g} --tol-utau {a.tol_utau:g} --out {a.out}`; "
+                     f"--max-steps {a.max_steps} --tol {a.tol:g} --tol-utau {a.tol_utau:g} --out <file>`; "
                      f"{len(rows)} channels in one serving pool, {time.perf_counter() - t0:.1f} s on one "
                      "MI355X.  D2Q9 4 x 2N, FP64, central-moment collision + SA, Dean start; "
                      "u_tau/target = the wall function's mean friction velocity over the one the "
