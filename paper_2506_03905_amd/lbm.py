@@ -310,6 +310,15 @@ class Lattice:
     def steps(self) -> int:
         return int(lib().lbm_steps(self.h))
 
+    def lbm_steps(self) -> int:
+        return int(lib().lbm_steps(self.h))
+
+    def lbm_ncell(self) -> int:
+        return int(lib().lbm_ncell(self.h))
+
+    def lbm_nwall(self) -> int:
+        return int(lib().lbm_nwall(self.h))
+
 
 class _View(Lattice):
     """A lattice handle owned by a pool slot (exports only)."""

@@ -706,6 +706,56 @@ def test_row_map_multi_block_perturbed_f64(q, nx, ny, nz, collision):
         assert np.abs(g.lbm_populations() - o.f()).max() < 1e-13
 
 
+@pytest.mark.parametrize("q,nx,ny,nz", [(19, 320, 16, 4), (9, 448, 16, 1)])
+def test_row_map_ragged_last_block_f64(q, nx, ny, nz):
+    """Rows of two blocks whose second block is partly beyond the row (64 and
+    192 active columns of 256): the staged odd step's pushes inside that
+    block, across its edge and through the periodic wrap, element-wise
+    against the oracle after 1, 2 and 9 more steps."""
+    lat = units.channel(5000.0, ny // 2)
+    u0 = _channel_u0(q, nx, ny, nz, lat["u_bulk"], amp=1e-3, seed=13)
+    o, g = _pair(q, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"],
+                 force=(lat["force"] * 10, 0, 0))
+    for n in (1, 1, 9):
+        o.step(n)
+        g.lbm_step(n)
+        _compare_f64(o, g)
+        assert np.abs(g.lbm_populations() - o.f()).max() < 1e-13
+
+
+def test_zero_steps_leave_the_state_alone():
+    """lbm_step(0) takes no step: the step count, populations and moments stay
+    bitwise the same."""
+    lat = units.channel(5000.0, 8)
+    u0 = _channel_u0(19, 128, 16, 4, lat["u_bulk"], amp=1e-3, seed=5)
+    _, g = _pair(19, 128, 16, 4, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"], force=(lat["force"], 0, 0))
+    g.lbm_step(3)
+    f0, (_, u0g, _) = g.lbm_populations(), g.lbm_moments()
+    g.lbm_step(0)
+    assert g.lbm_steps() == 3
+    assert np.array_equal(g.lbm_populations(), f0)
+    assert np.array_equal(g.lbm_moments()[1], u0g)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_rest_state_stays_at_rest(precision):
+    """No flow and no force on the row-mapped D3Q19 channel: the populations
+    stay at equilibrium, so u stays exactly 0 and the wall function returns
+    u_tau = 0 (a zero velocity at F gives a zero friction velocity); nu_tilde
+    decays by destruction alone, as in the oracle."""
+    nx, ny, nz = 128, 16, 4
+    lat = units.channel(5000.0, ny // 2)
+    u0 = np.zeros((3, nz, ny, nx))
+    o, g = _pair(19, nx, ny, nz, scheme=O.BB_SLIP, u0=u0, nu=lat["nu"], precision=precision)
+    for n in (1, 1, 8):
+        o.step(n)
+        g.lbm_step(n)
+        _, ug, _ = g.lbm_moments()
+        assert not np.any(ug), np.abs(ug).max()
+        assert not np.any(g.lbm_wall()["utau"])
+        tol = 1e-12 if precision == "f64" else 1e-6
+        assert _rel_l2(g.lbm_nu_tilde(), o.nt()) < tol
+
 @pytest.mark.parametrize("q,nx,ny,nz", [(19, 512, 16, 4), (9, 768, 16, 1)])
 def test_row_map_multi_block_perturbed_f32(q, nx, ny, nz):
     """The same lattices with FP32 storage and arithmetic (the benchmark's
